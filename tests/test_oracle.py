@@ -1,0 +1,413 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+exact integrals done a different way, invariants, brute force on tiny grids,
+finite differences, or rigorous bounds.  Runs on the CPU.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hmgref as O
+from paper_2301_08911_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LAM, MU = 15.0 / 26.0, 5.0 / 13.0          # E = 1, nu = 0.3
+
+
+@pytest.fixture(scope="module")
+def K0():
+    return O.element_stiffness(1.0, 0.3)
+
+
+@pytest.fixture(scope="module")
+def chi():
+    return O.unit_strain_displacements()
+
+
+def k0_by_1d_integrals(lam, mu):
+    """Independent K0: exact 1D integrals of linear shape functions, tensorized.
+
+    K0[3a+p, 3b+q] = lam I(a,p;b,q) + mu (delta_pq sum_i I(a,i;b,i) + I(a,q;b,p)),
+    I(a,i;b,j) = int d_i N_a d_j N_b over the unit cube.
+    """
+    M = np.array([[1 / 3, 1 / 6], [1 / 6, 1 / 3]])
+    S = np.array([[1.0, -1.0], [-1.0, 1.0]])
+    C = np.array([[-0.5, -0.5], [0.5, 0.5]])
+
+    def integral(a, i, b, j):
+        v = 1.0
+        for k in range(3):
+            ak, bk = (a >> k) & 1, (b >> k) & 1
+            if k == i and k == j:
+                v *= S[ak, bk]
+            elif k == i:
+                v *= C[ak, bk]
+            elif k == j:
+                v *= C[bk, ak]
+            else:
+                v *= M[ak, bk]
+        return v
+
+    K = np.zeros((24, 24))
+    for a, b, p, q in itertools.product(range(8), range(8), range(3), range(3)):
+        K[3 * a + p, 3 * b + q] = lam * integral(a, p, b, q) + mu * (
+            (p == q) * sum(integral(a, i, b, i) for i in range(3)) + integral(a, q, b, p))
+    return K
+
+
+# --------------------------------------------------------------------- element
+
+def test_constitutive_closed_form():
+    D = O.constitutive_matrix(1.0, 0.3)
+    assert abs(D[0, 0] - 35 / 26) < 1e-15 and abs(D[0, 1] - 15 / 26) < 1e-15
+    assert abs(D[3, 3] - 5 / 13) < 1e-15 and D[0, 3] == 0.0
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.2, 0.45])
+def test_k0_matches_exact_integrals(nu):
+    lam, mu = O.lame(1.0, nu)
+    assert np.abs(O.element_stiffness(1.0, nu) - k0_by_1d_integrals(lam, mu)).max() < 1e-14
+
+
+def test_k0_symmetric_psd_six_rigid_modes(K0):
+    assert np.abs(K0 - K0.T).max() < 1e-16
+    ev = np.linalg.eigvalsh(K0)
+    assert (np.abs(ev) < 1e-12).sum() == 6
+    assert ev.min() > -1e-12
+
+
+def test_unit_strain_energy_is_D(K0, chi):
+    # (chi^i)^T K0 chi^j = D_ij: the brick reproduces a homogeneous strain exactly
+    assert np.abs(chi @ K0 @ chi.T - O.constitutive_matrix()).max() < 1e-14
+
+
+def test_load_template_closed_form(K0, chi):
+    # g^i_{b,k} = 1/4 sum_j sigma^i_kj (+1 if bit j of b else -1), sigma^i = D e^i
+    D = O.constitutive_matrix()
+    voigt = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 0): 3, (1, 2): 4, (2, 1): 4,
+             (0, 2): 5, (2, 0): 5}
+    for i in range(6):
+        g = K0 @ chi[i]
+        sig = np.array([[D[voigt[(k, j)], i] for j in range(3)] for k in range(3)])
+        ref = np.zeros(24)
+        for b in range(8):
+            sgn = np.array([1.0 if (b >> j) & 1 else -1.0 for j in range(3)])
+            ref[3 * b:3 * b + 3] = 0.25 * sig @ sgn
+        assert np.abs(g - ref).max() < 1e-15
+
+
+# --------------------------------------------------------------------- assembly
+
+def test_csr_equals_elementwise_and_kills_translations(K0):
+    shape = (4, 6, 8)
+    rho = I.uniform_density(shape, 3)
+    s = O.simp_scale(rho)
+    K = O.assemble_stiffness(s, shape, K0)
+    n = s.size
+    assert K.nnz == 81 * 3 * n
+    u = I.random_signed_field(shape, 4, ncases=2).transpose(0, 2, 1)
+    Ku_csr = (K @ u.reshape(2, 3 * n).T).T.reshape(2, n, 3)
+    Ku_el = O.apply_elementwise(s, shape, K0, u)
+    assert np.abs(Ku_csr - Ku_el).max() < 1e-13
+    t = np.tile(np.array([0.3, -1.0, 2.0]), n)
+    assert np.abs(K @ t).max() < 1e-13
+    assert abs(K - K.T).max() < 1e-15
+
+
+def test_loads_sum_to_zero_and_vanish_on_uniform_cell(K0, chi):
+    shape = (4, 4, 6)
+    s = O.simp_scale(I.uniform_density(shape, 1))
+    f = O.load_vectors(s, shape, K0, chi)
+    assert np.abs(f.sum(axis=1)).max() < 1e-14
+    f1 = O.load_vectors(np.full(s.size, 0.7), shape, K0, chi)
+    assert np.abs(f1).max() < 1e-15
+
+
+def test_loads_equal_K_times_global_linear_field_in_interior(K0, chi):
+    # Away from the periodic seam, f^i equals K applied to the global linear
+    # displacement of unit strain i (Eq. el-force with chi in global coordinates)
+    shape = (6, 6, 6)
+    s = O.simp_scale(I.uniform_density(shape, 7))
+    K = O.assemble_stiffness(s, shape, K0)
+    f = O.load_vectors(s, shape, K0, chi)
+    n = s.size
+    v = np.arange(n)
+    X = np.stack([v % 6, (v // 6) % 6, v // 36], axis=1).astype(float)
+    lin = {0: lambda x: (x[:, 0], 0 * x[:, 0], 0 * x[:, 0]),
+           3: lambda x: (x[:, 1] / 2, x[:, 0] / 2, 0 * x[:, 0]),
+           4: lambda x: (0 * x[:, 0], x[:, 2] / 2, x[:, 1] / 2)}
+    interior = np.all((X >= 1) & (X <= 4), axis=1)
+    for i, fn in lin.items():
+        U = np.stack(fn(X), axis=1).ravel()
+        KU = (K @ U).reshape(n, 3)
+        assert np.abs(KU[interior] - f[i][interior]).max() < 1e-13
+
+
+# --------------------------------------------------------------------- solve
+
+def test_cg_matches_dense_brute_force_4cubed(K0, chi):
+    shape = (4, 4, 4)
+    rho = I.uniform_density(shape, 11)
+    s = O.simp_scale(rho)
+    K = O.assemble_stiffness(s, shape, K0)
+    f = O.translation_projection(O.load_vectors(s, shape, K0, chi))
+    u_dense = O.dense_pinned_solve(K, f)
+    u_cg, it, rr = O.pcg_solve(K, f, tol=1e-12, eps_abs=0.0)
+    assert (rr <= 1e-12).all()
+    scale = np.abs(u_dense).max()
+    assert np.abs(u_cg - u_dense).max() <= 1e-10 * scale
+    C1 = O.elastic_tensor(s, u_dense, shape, K0, chi)
+    C2 = O.elastic_tensor(s, u_cg, shape, K0, chi)
+    assert np.abs(C1 - C2).max() < 1e-12 * np.abs(C1).max()
+
+
+def test_solid_cell_returns_base_tensor(K0, chi):
+    shape = (4, 4, 4)
+    s = O.simp_scale(np.ones(64))
+    u, it, rr = O.solve_cases(s, shape)
+    assert (it == 0).all()
+    C = O.elastic_tensor(s, u, shape, K0, chi)
+    assert np.abs(C - O.constitutive_matrix()).max() < 1e-9
+
+
+def _laminate_closed_form(s_profile, lam, mu, nu):
+    a = np.mean(s_profile)
+    H = 1.0 / np.mean(1.0 / np.asarray(s_profile))
+    c = nu / (1.0 - nu)
+    C = np.zeros((6, 6))
+    C[0, 0] = C[1, 1] = a * (lam + 2 * mu - c * lam) + c * H * lam
+    C[0, 1] = C[1, 0] = a * (1 - c) * lam + c * H * lam
+    C[2, 2] = H * (lam + 2 * mu)
+    C[0, 2] = C[2, 0] = C[1, 2] = C[2, 1] = H * lam
+    C[3, 3] = a * mu
+    C[4, 4] = C[5, 5] = H * mu
+    return C
+
+
+def test_laminate_golden_4cubed(K0, chi):
+    shape = (4, 4, 4)
+    rho = I.z_laminate(shape, [1, 1, 0.5, 0.5])
+    s = O.simp_scale(rho, Emin=0.0)
+    u, it, rr = O.solve_cases(s, shape)
+    C = O.elastic_tensor(s, u, shape, K0, chi)
+    gold = np.loadtxt(os.path.join(GOLDEN, "laminate_4.txt"))
+    assert np.abs(C - gold).max() < 1e-9
+
+
+@pytest.mark.parametrize("shape,profile", [((4, 6, 8), [0.2, 1, 1, 0.4, 0.9, 0.05, 0.6, 1.0]),
+                                           ((6, 4, 6), [1e-3, 1, 0.5, 1, 1e-3, 0.3])])
+def test_laminate_closed_form_any_profile(K0, chi, shape, profile):
+    rho = I.z_laminate(shape, profile)
+    s = O.simp_scale(rho)
+    u, it, rr = O.solve_cases(s, shape)
+    C = O.elastic_tensor(s, u, shape, K0, chi)
+    ref = _laminate_closed_form(s.reshape(shape[2], -1)[:, 0], LAM, MU, 0.3)
+    assert np.abs(C - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------- bounds & symmetry
+
+@pytest.fixture(scope="module")
+def random_cell():
+    shape = (6, 6, 6)
+    rho = I.smoothed_noise_density(shape, 5, 0.3, sigma=1.0)
+    s = O.simp_scale(rho)
+    u, it, rr = O.solve_cases(s, shape)
+    K0 = O.element_stiffness()
+    chi = O.unit_strain_displacements()
+    return shape, rho, s, u, O.elastic_tensor(s, u, shape, K0, chi)
+
+
+def test_tensor_symmetric_psd_within_voigt_reuss(random_cell):
+    shape, rho, s, u, C = random_cell
+    assert np.abs(C - C.T).max() < 1e-12
+    assert np.linalg.eigvalsh(C).min() > 0
+    assert np.linalg.eigvalsh(O.voigt_bound(s) - C).min() > -1e-12
+    assert np.linalg.eigvalsh(C - O.reuss_bound(s)).min() > -1e-12
+
+
+def test_binary_cell_below_hashin_shtrikman_bulk(random_cell):
+    shape, rho, s, u, C = random_cell
+    f1 = float((rho == 1.0).mean())
+    Ks, Gs = LAM + 2 * MU / 3, MU
+    s_void = O.simp_scale(np.array([1e-3]))[0]
+    bound = O.hs_bulk_upper(f1, Ks, Gs, Ks * s_void)
+    assert O.bulk_modulus(C) <= bound + 1e-12
+
+
+def test_hs_bulk_formula_known_values():
+    # void phase: 4 f G K / (3 K (1-f) + 4 G), values at f = 0.15, 0.2, 0.3
+    Ks, Gs = LAM + 2 * MU / 3, MU
+    for f, ref in ((0.15, 0.052493), (0.2, 0.072464), (0.3, 0.116959)):
+        assert abs(O.hs_bulk_upper(f, Ks, Gs, 0.0) - ref) < 5e-7
+
+
+def test_periodic_shift_and_axis_permutation_invariance(random_cell):
+    shape, rho, s, u, C = random_cell
+    K0, chi = O.element_stiffness(), O.unit_strain_displacements()
+    r3 = rho.reshape(shape[2], shape[1], shape[0])
+    shifted = np.roll(r3, shift=(2, -1, 3), axis=(0, 1, 2))
+    s2 = O.simp_scale(shifted)
+    u2, _, _ = O.solve_cases(s2, shape)
+    C2 = O.elastic_tensor(s2, u2, shape, K0, chi)
+    assert np.abs(C2 - C).max() < 1e-9 * np.abs(C).max()
+    # swap x and y: voigt permutation 0<->1, 4(23)<->5(13), 3 fixed
+    swapped = np.ascontiguousarray(r3.transpose(0, 2, 1))
+    s3 = O.simp_scale(swapped)
+    u3, _, _ = O.solve_cases(s3, shape)
+    C3 = O.elastic_tensor(s3, u3, shape, K0, chi)
+    perm = [1, 0, 2, 3, 5, 4]
+    assert np.abs(C3 - C[np.ix_(perm, perm)]).max() < 1e-9 * np.abs(C).max()
+
+
+def test_reflection_sign_pattern(random_cell):
+    shape, rho, s, u, C = random_cell
+    K0, chi = O.element_stiffness(), O.unit_strain_displacements()
+    r3 = rho.reshape(shape[2], shape[1], shape[0])
+    refl = np.ascontiguousarray(r3[:, :, ::-1])
+    s2 = O.simp_scale(refl)
+    u2, _, _ = O.solve_cases(s2, shape)
+    C2 = O.elastic_tensor(s2, u2, shape, K0, chi)
+    sig = np.array([1, 1, 1, -1, 1, -1.0])
+    assert np.abs(C2 - np.outer(sig, sig) * C).max() < 1e-9 * np.abs(C).max()
+
+
+# --------------------------------------------------------------------- sensitivity
+
+def test_sensitivity_central_difference():
+    shape = (4, 4, 4)
+    K0, chi = O.element_stiffness(), O.unit_strain_displacements()
+    rho = I.uniform_density(shape, 21, mean=0.5).ravel()
+    W = np.random.default_rng(0).standard_normal((6, 6))
+
+    def objective(r):
+        s = O.simp_scale(r)
+        u, _, _ = O.solve_cases(s, shape, tol=1e-13)
+        return float((W * O.elastic_tensor(s, u, shape, K0, chi)).sum())
+
+    s = O.simp_scale(rho)
+    u, _, _ = O.solve_cases(s, shape, tol=1e-13)
+    g = O.sensitivity(rho, u, shape, K0, chi, W)
+    h = 1e-5
+    for e in (0, 17, 42, 63):
+        rp, rm = rho.copy(), rho.copy()
+        rp[e] += h
+        rm[e] -= h
+        fd = (objective(rp) - objective(rm)) / (2 * h)
+        assert abs(fd - g[e]) <= 1e-6 * max(1e-6, abs(g[e]))
+
+
+def test_sensitivity_euler_identity():
+    # C is homogeneous of degree 1 in s; with Emin = 0, s = rho^p and
+    # sum_e rho_e dC/drho_e = p C.
+    shape = (4, 4, 6)
+    K0, chi = O.element_stiffness(), O.unit_strain_displacements()
+    rho = I.uniform_density(shape, 8, mean=0.4).ravel() + 0.05
+    s = O.simp_scale(rho, Emin=0.0)
+    u, _, _ = O.solve_cases(s, shape)
+    C = O.elastic_tensor(s, u, shape, K0, chi)
+    for i, j in ((0, 0), (0, 1), (3, 3), (2, 5)):
+        W = np.zeros((6, 6))
+        W[i, j] = 1.0
+        g = O.sensitivity(rho, u, shape, K0, chi, W, Emin=0.0)
+        assert abs((rho * g).sum() - 3.0 * C[i, j]) < 1e-12 * max(1.0, abs(C).max())
+
+
+def test_sensitivity_sign_for_stiffness_objectives(random_cell):
+    shape, rho, s, u, C = random_cell
+    K0, chi = O.element_stiffness(), O.unit_strain_displacements()
+    for W in (O.bulk_weights(), O.shear_weights()):
+        g = O.sensitivity(rho, u, shape, K0, chi, W)
+        assert g.max() <= 1e-15
+
+
+# --------------------------------------------------------------------- filter & OC
+
+def test_filter_weights_closed_form():
+    shape = (5, 5, 5)
+    x = np.zeros(125)
+    x[62] = 1.0                                     # centre voxel (2,2,2)
+    y = O.density_filter(x, shape, 2.0).reshape(5, 5, 5)
+    total = 2 + 6 * 1 + 12 * (2 - math.sqrt(2)) + 8 * (2 - math.sqrt(3))
+    assert abs(total - 17.17303) < 1e-5
+    assert abs(y[2, 2, 2] - 2 / total) < 1e-15
+    assert abs(y[2, 2, 3] - 1 / total) < 1e-15
+    assert abs(y[2, 3, 3] - (2 - math.sqrt(2)) / total) < 1e-15
+    assert abs(y[3, 3, 3] - (2 - math.sqrt(3)) / total) < 1e-15
+    assert abs(y[2, 2, 4]) == 0.0
+
+
+def test_filter_stochastic_mean_preserving_symmetric():
+    shape = (6, 4, 8)
+    rng = np.random.default_rng(3)
+    x, z = rng.random(192), rng.random(192)
+    assert np.abs(O.density_filter(np.ones(192), shape) - 1).max() < 1e-15
+    assert abs(O.density_filter(x, shape).mean() - x.mean()) < 1e-15
+    assert abs(O.density_filter(x, shape) @ z - x @ O.density_filter(z, shape)) < 1e-13
+
+
+def test_oc_hits_volume_and_respects_limits():
+    rng = np.random.default_rng(4)
+    x = np.clip(rng.random(4096) * 0.6, 1e-3, 1)
+    g = -rng.random(4096) * 1e-3
+    xn, lam = O.oc_update(x, g, 0.3)
+    assert abs(xn.mean() - 0.3) < 1e-12
+    assert (xn >= 1e-3 - 1e-16).all() and (xn <= 1 + 1e-16).all()
+    assert (np.abs(xn - x) <= 0.05 + 1e-15).all()
+    # mean(x_new(lambda)) is non-increasing in lambda
+    means = [O.oc_candidate(x, g, l, 0.05, 0.5, 1e-3).mean() for l in np.logspace(-6, 0, 25)]
+    assert all(a >= b - 1e-15 for a, b in zip(means, means[1:]))
+
+
+# --------------------------------------------------------------------- multigrid reference
+
+def test_prolongation_reproduces_constants_and_galerkin_kills_translations(K0):
+    shape = (8, 4, 6)
+    P = O.prolongation(shape)
+    nc = 4 * 2 * 3
+    c = np.tile([1.0, 2.0, -0.5], nc)
+    assert np.abs(P @ c - np.tile([1.0, 2.0, -0.5], 8 * 4 * 6)).max() < 1e-15
+    s = O.simp_scale(I.uniform_density(shape, 2))
+    K = O.assemble_stiffness(s, shape, K0)
+    Kc = (P.T @ K @ P).tocsr()
+    assert np.abs(Kc @ c).max() < 1e-13
+    st = O.stencil_blocks(Kc, (4, 2, 3))
+    # at a coarse dim of 2 the +1 and -1 neighbours alias; only the sum is defined
+    assert st.shape == (27, 3, 3, nc)
+
+
+def test_prolongation_interpolates_linear_in_interior():
+    shape = (8, 8, 8)
+    P = O.prolongation(shape)
+    X = np.arange(4)
+    Zc, Yc, Xc = np.meshgrid(X, X, X, indexing="ij")
+    coarse = np.stack([Xc.ravel() + 2 * Yc.ravel(), 0 * Xc.ravel(), Zc.ravel()], 1).ravel()
+    fine = (P @ coarse).reshape(-1, 3)
+    v = np.arange(512)
+    x, y, z = v % 8, (v // 8) % 8, v // 64
+    inner = (x < 7) & (y < 7) & (z < 7)
+    assert np.abs(fine[inner, 0] - (x + 2 * y)[inner] / 2).max() < 1e-15
+    assert np.abs(fine[inner, 2] - z[inner] / 2).max() < 1e-15
+
+
+# --------------------------------------------------------------------- generators
+
+def test_generators_counts_and_mean():
+    rho = I.uniform_density((16, 16, 16), 0)
+    assert abs(rho.mean() - 0.3) < 1e-15 and rho.max() < 0.7 and rho.min() >= 0
+    d = I.smoothed_noise_density((16, 16, 16), 3, 0.2)
+    assert int((d == 1.0).sum()) == round(0.2 * 4096)
+    assert set(np.unique(d)) == {1e-3, 1.0}
+    assert abs(I.box_downsample(d, 4).mean() - d.mean()) < 1e-15
+    u = I.uniform01(7, 0, 1000)
+    assert u.min() >= 0 and u.max() < 1 and abs(u.mean() - 0.5) < 0.05
+
+
+def test_splitmix64_reference_vector():
+    # SplitMix64 with state 0: first output of the published generator
+    # (state += golden gamma, then mix) is 0xE220A8397B1DCDAF.
+    assert int(I.splitmix64(np.array([0], dtype=np.uint64))[0]) == 0xE220A8397B1DCDAF
