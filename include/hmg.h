@@ -1,0 +1,193 @@
+/*
+ * hmg.h - C ABI of the MI355X (gfx950) periodic homogenization solver.
+ *
+ * The library computes, for a periodic unit cell of nx*ny*nz unit voxels
+ * (8-node trilinear bricks), the six macro-strain fluctuation fields, the
+ * homogenized elasticity tensor C^H and its element sensitivities, following
+ * Zhang et al., arXiv 2301.08911:
+ *   - problem statement: Sec. 3.1, Eq. (opt-prob);
+ *   - loads, FE solve, C^H:  Sec. 3.2, Eq. (el-force), (fem), (elasttensor);
+ *   - sensitivities:         Sec. 3.2, Eq. (obj-grad), (ch-sens);
+ *   - multigrid hierarchy:   Sec. 3.3 (Galerkin K_{l+1} = R K_l I, Alg. 1),
+ *                            Sec. 4.2 (macro strain, relaxation split,
+ *                            level-2 stencil assembly, null-space removal);
+ *   - filter and OC update:  Sec. 5.2 and Sec. 6 parameters.
+ * The FE systems are solved by conjugate gradients preconditioned with one
+ * geometric-multigrid V-cycle (damped 3x3 block-Jacobi smoothing, trilinear
+ * prolongation, restriction = its transpose, FP64 direct coarsest solve).
+ *
+ * Conventions shared by every entry point
+ *   - Index of vertex / element (x, y, z): idx = x + nx*(y + ny*z); the grid is
+ *     periodic, so there are n = nx*ny*nz vertices and n elements.  Element
+ *     idx has local node a = a0 + 2 a1 + 4 a2 at vertex (x+a0, y+a1, z+a2).
+ *   - Nodal fields of the six load cases are "case-major SoA":
+ *     u[(c*3 + k)*n + idx], case c in 0..5 (Voigt 11,22,33,12,23,13), comp k.
+ *     Their element type is the context's field type: double for HMG_FP64,
+ *     float otherwise.
+ *   - Displacements are in element units (element-relative macro strain,
+ *     Sec. 4.2 Eq. (macro-strain)); they are defined up to a translation and
+ *     are returned with zero mean per case and component.
+ *   - C^H is in units of E0, row-major 6x6, Voigt order 11,22,33,12,23,13
+ *     (Sec. 3.2), normalised by |Omega| = n.
+ *   - Pointers named *_dev are device pointers on the context's device; the
+ *     caller owns them and they must stay valid until the call's work has
+ *     completed on the context's stream.  Host arrays are plain C arrays.
+ *   - Calls enqueue on the context's HIP stream.  Calls with host outputs
+ *     (iters_out, relres_out, C_out, lambda_out, status checks of
+ *     hmg_set_density) synchronize that stream before returning.
+ *   - Errors are reported by status code only; nothing throws across the ABI.
+ *     hmg_last_error() gives a per-context message.  Argument errors leave the
+ *     context state unchanged.
+ */
+#ifndef HMG_H
+#define HMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmg_ctx_s* hmg_ctx;
+
+typedef enum {
+  HMG_OK = 0,
+  HMG_E_INVALID = 1,       /* bad argument, shape, density value or limit      */
+  HMG_E_OOM = 2,           /* device allocation failed                          */
+  HMG_E_DEVICE = 3,        /* a HIP runtime call failed                         */
+  HMG_E_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the partial state  */
+  HMG_E_STATE = 5          /* called before its prerequisite step               */
+} hmg_status;
+
+typedef enum {
+  HMG_FP64 = 0,        /* all fields, stencils and reductions in double        */
+  HMG_FP32 = 1,        /* float fields/stencils, FP64 dots and coarsest solve  */
+  HMG_MIXED_BF16 = 2,  /* reserved: bf16 streamed operands (not yet built)     */
+  HMG_MIXED_FP16 = 3   /* reserved: fp16 streamed operands (not yet built)     */
+} hmg_precision;
+
+/* Solver configuration (Sec. 6 defaults: E0 = 1, nu = 0.3, p = 3). */
+typedef struct hmg_config {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 4                        */
+  double E0;              /* Young's modulus of the solid (> 0)               */
+  double nu;              /* Poisson ratio, in (-1, 0.5)                      */
+  double penal;           /* SIMP exponent p (>= 1)                           */
+  double Emin;            /* stiffness floor: s = Emin + rho^p (E0 - Emin)    */
+  int32_t levels;         /* multigrid levels; 0 = coarsen 1:2 while every
+                             axis stays even and the coarse mesh is >= 4 per
+                             axis (Sec. 3.3)                                   */
+  double omega;           /* damped block-Jacobi weight; 0 selects 0.6         */
+  int32_t nu_pre;         /* pre-smoothing sweeps; only 1 is supported          */
+  int32_t nu_post;        /* post-smoothing sweeps; only 1 is supported         */
+  int32_t precision;      /* hmg_precision                                     */
+  int32_t replace_every;  /* recompute r = f - K x every k PCG iterations
+                             (0 = never)                                      */
+} hmg_config;
+
+/* Create a context for one cell on the current HIP device.  `hip_stream` is a
+ * hipStream_t (NULL = default stream).  Allocates the multigrid hierarchy and
+ * the PCG work fields in device memory.  Fails with HMG_E_INVALID for a bad
+ * configuration (shape, material, levels, or a coarsest grid above the direct
+ * solver's limit of 6144 unknowns) and HMG_E_OOM if the device is too small. */
+hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out);
+
+/* Release every device buffer of the context.  NULL is accepted. */
+hmg_status hmg_destroy(hmg_ctx ctx);
+
+/* Set the physical (already filtered) element densities rho~ in [0, 1]:
+ * rho_dev is float[n].  Computes s_e = Emin + rho^p (E0 - Emin) (SIMP,
+ * Sec. 3.2), the block-Jacobi inverses, the Galerkin stencils of every coarse
+ * level (level 2 from the densities as in Sec. 4.2 Eq. (st-level-2), deeper
+ * levels from the finer stencil) and the FP64 factor of the coarsest level.
+ * A NaN or a value outside [0, 1] gives HMG_E_INVALID (checked on the device;
+ * this call synchronizes). */
+hmg_status hmg_set_density(hmg_ctx ctx, const float* rho_dev);
+
+/* Solve K u^i = f^i for the six unit macro strains (Sec. 3.2 Eq. (fem),
+ * loads Eq. (el-force) with the element-relative chi of Sec. 4.2).
+ *   rel_tol   a case stops when ||f - K u|| <= max(rel_tol ||f||, eps_abs)
+ *             with eps_abs = 1e-12 sqrt(n) (lambda1 + 2 mu1) mean(s), where
+ *             lambda1, mu1 are the Lame constants of (E = 1, nu);
+ *             a case with ||f|| <= eps_abs is solved by u = 0 in 0 iterations.
+ *   max_iter  PCG iteration limit per case (> 0).
+ *   init      0 = zero initial guess, 1 = the previous solution of this
+ *             context, 2 = u0_dev (field type, case-major SoA).
+ *   iters_out PCG iterations per case (host int32[6]).
+ *   relres_out ||f - K u|| / ||f|| per case, recomputed at the end
+ *             (host double[6]; 0 for a trivial case).
+ * Returns HMG_E_NOT_CONVERGED if a case hit max_iter (outputs still filled),
+ * HMG_E_STATE before hmg_set_density. */
+hmg_status hmg_solve_cases(hmg_ctx ctx, double rel_tol, int32_t max_iter, int32_t init,
+                           const void* u0_dev, int32_t iters_out[6], double relres_out[6]);
+
+/* Homogenized tensor of the last solve, Sec. 3.2 Eq. (elasttensor):
+ * C_ij = (1/n) sum_e s_e (chi^i - u^i_e)^T K0 (chi^j - u^j_e), host double[36].
+ * HMG_E_STATE before hmg_solve_cases. */
+hmg_status hmg_elastic_tensor(hmg_ctx ctx, double C_out[36]);
+
+/* Element sensitivities of sum_ij W_ij C_ij with respect to rho~_e,
+ * Sec. 3.2 Eq. (obj-grad) and (ch-sens), read per element:
+ *   dfdrho[e] = (1/n) p rho_e^(p-1) (E0 - Emin) sum_ij W_ij d_e^i.K0 d_e^j,
+ * d_e^i = chi^i - u^i_e.  W is host double[36] (row-major, e.g. dF/dC^H);
+ * dfdrho_dev is float[n].  HMG_E_STATE before hmg_solve_cases. */
+hmg_status hmg_sensitivity(hmg_ctx ctx, const double W[36], float* dfdrho_dev);
+
+/* Optimality-criteria update (Sec. 3.3 step 4; parameters of Sec. 6), in place
+ * on the design field x_dev (float[n]) with gradient dfdx_dev (float[n]):
+ *   x_new = clamp(x * (max(0, -g)/lambda)^damp, max(xmin, x - move), min(1, x + move)),
+ * with lambda found by bisection of log(lambda) on [1e-40, 1e40] so that
+ * mean(x_new) = volfrac.  The chosen lambda is written to *lambda_out (host;
+ * may be NULL).  Needs only hmg_create. */
+hmg_status hmg_oc_update(hmg_ctx ctx, float* x_dev, const float* dfdx_dev, double volfrac,
+                         double move, double damp, double xmin, double* lambda_out);
+
+/* Periodic density filter (Sec. 5.2: rho~ = conv(x); radius 2 in Sec. 6):
+ * out = H in, with weights max(0, radius - |d|) over integer offsets d,
+ * normalised to sum 1.  H is symmetric, so `adjoint` (apply H^T, used to take
+ * dF/drho~ back to dF/dx) gives the same result.  in_dev/out_dev are float[n]
+ * and must not overlap.  radius in (1, 4]. */
+hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double radius,
+                      int32_t adjoint);
+
+/* Copy the last solution (field type, case-major SoA, zero mean) to u_dev. */
+hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* hmg_last_error(hmg_ctx ctx);
+
+/* ---- inspection entry points (used by the parity tests) ------------------ */
+
+/* Number of multigrid levels and the cells per axis of one level. */
+hmg_status hmg_num_levels(hmg_ctx ctx, int32_t* levels_out);
+hmg_status hmg_level_dims(hmg_ctx ctx, int32_t level, int32_t dims_out[3]);
+
+/* y = K_l u for the six cases on one level (field type, case-major SoA at that
+ * level's size).  Level 0 is the matrix-free operator of Sec. 4.2
+ * Eq. (st-assemb); deeper levels use the stored Galerkin stencils. */
+hmg_status hmg_apply_operator(hmg_ctx ctx, int32_t level, const void* u_dev, void* y_dev);
+
+/* The 27-point stencil of level l: out[((d*3 + i)*3 + j)*n_l + v] is the
+ * (i, j) entry of the 3x3 block coupling vertex v to v + offset(d), with
+ * d = (dx+1) + 3 (dy+1) + 9 (dz+1).  Level 0 is assembled from the densities
+ * for this call; deeper levels are the stored Galerkin stencils (Sec. 4.2). */
+hmg_status hmg_get_stencil(hmg_ctx ctx, int32_t level, void* out_dev);
+
+/* The six macro-strain load vectors f^i (field type, case-major SoA),
+ * Sec. 4.2 "Enforce macro strain". */
+hmg_status hmg_load_vectors(hmg_ctx ctx, void* f_dev);
+
+/* z = M r: one application of the multigrid V-cycle preconditioner on the
+ * six cases (field type, case-major SoA at level 0). */
+hmg_status hmg_vcycle(hmg_ctx ctx, const void* r_dev, void* z_dev);
+
+/* Grid transfer between level l and l+1: direction 0 restricts (R = P^T) a
+ * level-l field into a level-(l+1) field; direction 1 prolongates (P) a
+ * level-(l+1) field into a level-l field (overwriting it). */
+hmg_status hmg_transfer(hmg_ctx ctx, int32_t level, int32_t direction, const void* in_dev,
+                        void* out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMG_H */

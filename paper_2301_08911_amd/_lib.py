@@ -1,0 +1,67 @@
+"""Loader of the in-tree HIP library; there is no fallback implementation."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmg.so")
+
+SYMBOLS = (
+    "hmg_create", "hmg_destroy", "hmg_set_density", "hmg_solve_cases", "hmg_elastic_tensor",
+    "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
+    "hmg_num_levels", "hmg_level_dims", "hmg_apply_operator", "hmg_get_stencil",
+    "hmg_load_vectors", "hmg_vcycle", "hmg_transfer",
+)
+
+
+class HmgConfig(ctypes.Structure):
+    """Mirror of ``hmg_config`` in include/hmg.h."""
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("E0", ctypes.c_double), ("nu", ctypes.c_double), ("penal", ctypes.c_double),
+        ("Emin", ctypes.c_double), ("levels", ctypes.c_int32), ("omega", ctypes.c_double),
+        ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("replace_every", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhmg.so (built by ``paper_2301_08911_amd.build``) and declare signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2301_08911_amd.build` "
+            "(the solver has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "hmg_create": ([P(HmgConfig), vp, P(vp)], i32),
+        "hmg_destroy": ([vp], i32),
+        "hmg_set_density": ([vp, vp], i32),
+        "hmg_solve_cases": ([vp, f64, i32, i32, vp, P(i32), P(f64)], i32),
+        "hmg_elastic_tensor": ([vp, P(f64)], i32),
+        "hmg_sensitivity": ([vp, P(f64), vp], i32),
+        "hmg_oc_update": ([vp, vp, vp, f64, f64, f64, f64, P(f64)], i32),
+        "hmg_filter": ([vp, vp, vp, f64, i32], i32),
+        "hmg_get_displacement": ([vp, vp], i32),
+        "hmg_last_error": ([vp], ctypes.c_char_p),
+        "hmg_num_levels": ([vp, P(i32)], i32),
+        "hmg_level_dims": ([vp, i32, P(i32)], i32),
+        "hmg_apply_operator": ([vp, i32, vp, vp], i32),
+        "hmg_get_stencil": ([vp, i32, vp], i32),
+        "hmg_load_vectors": ([vp, vp], i32),
+        "hmg_vcycle": ([vp, vp, vp], i32),
+        "hmg_transfer": ([vp, i32, i32, vp, vp], i32),
+    }
+    for name, (args, ret) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ret
+    _lib = lib
+    return lib

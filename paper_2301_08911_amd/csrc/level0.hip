@@ -1,0 +1,682 @@
+// Level-0 (finest grid) kernels: the matrix-free SIMP-weighted stiffness
+// operator and everything fused around it.
+//
+// Operator (Sec. 4.2, Eq. st-assemb):  [K u]_v = sum_{e ∋ v} s_e K0[loc_e(v), :] u_e.
+// The paper evaluates it vertex by vertex with one warp per incident element;
+// here it is evaluated element by element in the Walsh-Hadamard mode basis of
+// the 8 nodal values, where K0 has 45 nonzeros instead of 576:
+//   u_hat = H u_e (separable butterflies), w_hat = s_e Kt u_hat, y_e = H w_hat.
+// A workgroup owns a tile of 63 x 7 vertex columns and marches along z.  The
+// vertex plane (tile plus a one-vertex halo) is staged in LDS; each thread owns
+// one element column, forms the x/y butterflies from LDS and the z butterfly
+// in registers against the previous plane, and keeps the z-half of its output
+// that belongs to the next vertex plane in registers.  The other half goes
+// through LDS so that each vertex gathers the four element columns around it.
+#include "hmg_internal.hpp"
+
+namespace hmg {
+namespace {
+
+constexpr int TXE = 64;  // element columns along x per tile (one wavefront)
+constexpr int TYE = 8;   // element rows along y per tile (wavefronts per block)
+constexpr int OX = TXE - 1, OY = TYE - 1;  // owned vertex columns per tile
+constexpr int PX = TXE + 1, PY = TYE + 1;  // staged vertex plane
+constexpr int NTHR = TXE * TYE;
+constexpr int NLOAD = 3 * PY * PX;
+constexpr int NSLOT = (NLOAD + NTHR - 1) / NTHR;
+
+struct TileGeom {
+  int ntx, nty, nzc, lz, ntiles;
+};
+
+__host__ __device__ inline int modp(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+TileGeom tile_geom(const Grid& g) {
+  TileGeom t;
+  t.ntx = (g.nx + OX - 1) / OX;
+  t.nty = (g.ny + OY - 1) / OY;
+  const int base = t.ntx * t.nty * NCASE;
+  int lz = g.nz;
+  while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 8192) lz = (lz + 1) / 2;
+  t.lz = lz;
+  t.nzc = (g.nz + lz - 1) / lz;
+  t.ntiles = t.ntx * t.nty * t.nzc;
+  return t;
+}
+
+// o[m0 + 2 m1] = sum_{b0,b1} (-1)^(m0 b0 + m1 b1) u[b0 + 2 b1]; self-inverse up to 4.
+template <typename T>
+__device__ __forceinline__ void bfly4(T u0, T u1, T u2, T u3, T& o0, T& o1, T& o2, T& o3) {
+  const T s0 = u0 + u1, d0 = u0 - u1, s1 = u2 + u3, d1 = u2 - u3;
+  o0 = s0 + s1;
+  o1 = d0 + d1;
+  o2 = s0 - s1;
+  o3 = d0 - d1;
+}
+
+// w_hat = s * Kt * u_hat with the block pattern documented in ModeK.
+template <typename T>
+__device__ __forceinline__ void mode_apply(const ModeK<T>& K, T s, const T (&uh)[8][3],
+                                           T (&wh)[8][3]) {
+  const T sab = s * K.ab, sb = s * K.b, scs = s * K.cs, sp = s * K.p, sq = s * K.q;
+  const T sfg = s * K.fg, sg = s * K.g, sz = s * K.z;
+  const T sn = sb * (uh[1][0] + uh[2][1] + uh[4][2]);
+  wh[1][0] = sab * uh[1][0] + sn;
+  wh[2][1] = sab * uh[2][1] + sn;
+  wh[4][2] = sab * uh[4][2] + sn;
+  T t = scs * (uh[1][1] + uh[2][0]);
+  wh[1][1] = t;
+  wh[2][0] = t;
+  t = scs * (uh[1][2] + uh[4][0]);
+  wh[1][2] = t;
+  wh[4][0] = t;
+  t = scs * (uh[2][2] + uh[4][1]);
+  wh[2][2] = t;
+  wh[4][1] = t;
+  wh[3][0] = sp * uh[3][0] + sq * uh[6][2];
+  wh[6][2] = sq * uh[3][0] + sp * uh[6][2];
+  wh[3][1] = sp * uh[3][1] + sq * uh[5][2];
+  wh[5][2] = sq * uh[3][1] + sp * uh[5][2];
+  wh[5][0] = sp * uh[5][0] + sq * uh[6][1];
+  wh[6][1] = sq * uh[5][0] + sp * uh[6][1];
+  const T st = sg * (uh[3][2] + uh[5][1] + uh[6][0]);
+  wh[3][2] = sfg * uh[3][2] + st;
+  wh[5][1] = sfg * uh[5][1] + st;
+  wh[6][0] = sfg * uh[6][0] + st;
+  wh[7][0] = sz * uh[7][0];
+  wh[7][1] = sz * uh[7][1];
+  wh[7][2] = sz * uh[7][2];
+  wh[0][0] = wh[0][1] = wh[0][2] = T(0);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over the block in a fixed order; result valid in thread 0.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NW; ++i) s += lds[i];
+  return s;
+}
+
+// Block index -> (case, tile).  Workgroups are dispatched to the 8 XCDs round
+// robin, so consecutive logical indices are gathered on one XCD: the six cases
+// of a tile (which share s) and neighbouring tiles (which share halos) then
+// meet in the same L2.
+__device__ __forceinline__ int logical_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, xcd = b & 7;
+  return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+template <typename T, class Op>
+__global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk,
+                                                   const T* __restrict__ s) {
+  __shared__ T plane[2][3][PY][PX];
+  __shared__ T contrib[4][3][TYE][TXE];
+  __shared__ double red[NTHR / 64];
+
+  const int j = logical_block();
+  const int c = j % NCASE;
+  const int tile = j / NCASE;
+  if (!op.active(c)) return;
+  const int tx = tile % tg.ntx;
+  const int rem = tile / tg.ntx;
+  const int ty = rem % tg.nty;
+  const int zc = rem / tg.nty;
+  const int x0 = tx * OX, y0 = ty * OY;
+  const int z0 = zc * tg.lz;
+  const int z1 = min(z0 + tg.lz, g.nz);
+  const int tid = threadIdx.x, lx = tid & (TXE - 1), ly = tid / TXE;
+  const int64_t nxy = (int64_t)g.nx * g.ny;
+
+  // Plane-load slots of this thread (same for every plane).
+  int64_t ld_xy[NSLOT];
+  int ld_lds[NSLOT], ld_k[NSLOT], ld_gx[NSLOT], ld_gy[NSLOT];
+  bool ld_own[NSLOT], ld_ok[NSLOT];
+#pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl) {
+    const int i = tid + sl * NTHR;
+    ld_ok[sl] = i < NLOAD;
+    const int ii = ld_ok[sl] ? i : 0;
+    const int k = ii / (PY * PX);
+    const int rr = ii - k * (PY * PX);
+    const int py = rr / PX, px = rr - py * PX;
+    const int ux = x0 - 1 + px, uy = y0 - 1 + py;
+    ld_gx[sl] = modp(ux, g.nx);
+    ld_gy[sl] = modp(uy, g.ny);
+    ld_xy[sl] = ld_gx[sl] + (int64_t)g.nx * ld_gy[sl];
+    ld_lds[sl] = (k * PY + py) * PX + px;
+    ld_k[sl] = k;
+    ld_own[sl] = px >= 1 && px <= OX && py >= 1 && py <= OY && ux < g.nx && uy < g.ny;
+  }
+  const int ex = modp(x0 - 1 + lx, g.nx), ey = modp(y0 - 1 + ly, g.ny);
+  const int64_t exy = ex + (int64_t)g.nx * ey;
+  const bool outv = lx >= 1 && ly >= 1 && (x0 - 1 + lx) < g.nx && (y0 - 1 + ly) < g.ny;
+
+  auto load_plane = [&](int buf, int zu) {
+    const int gz = modp(zu, g.nz);
+    const bool ownz = zu >= z0 && zu < z1;
+    const int64_t zoff = nxy * gz;
+    T* base = &plane[buf][0][0][0];
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl)
+      if (ld_ok[sl])
+        base[ld_lds[sl]] =
+            op.load(c, ld_k[sl], zoff + ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz);
+  };
+  auto plane_modes = [&](int buf, T (&tm)[4][3], T (&own)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T u0 = plane[buf][k][ly][lx], u1 = plane[buf][k][ly][lx + 1];
+      const T u2 = plane[buf][k][ly + 1][lx], u3 = plane[buf][k][ly + 1][lx + 1];
+      own[k] = u0;
+      bfly4(u0, u1, u2, u3, tm[0][k], tm[1][k], tm[2][k], tm[3][k]);
+    }
+  };
+
+  double acc0 = 0.0, acc1 = 0.0;
+  T tp[4][3], ga[4][3], uown[3];
+  load_plane(0, z0 - 1);
+  __syncthreads();
+  plane_modes(0, tp, uown);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ga[q][k] = T(0);
+  int cur = 0;
+  for (int ez = z0 - 1; ez < z1; ++ez) {
+    const int nxt = cur ^ 1;
+    load_plane(nxt, ez + 1);
+    __syncthreads();
+    T tn[4][3], unext[3];
+    plane_modes(nxt, tn, unext);
+    const T se = s[nxy * modp(ez, g.nz) + exy];
+    T uh[8][3], wh[8][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        uh[q][k] = tp[q][k] + tn[q][k];      // m2 = 0
+        uh[q + 4][k] = tp[q][k] - tn[q][k];  // m2 = 1
+      }
+    mode_apply(mk, se, uh, wh);
+    if (ez >= z0) {
+      T gq[4][3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gq[q][k] = ga[q][k] + (wh[q][k] + wh[q + 4][k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        T y0v, y1v, y2v, y3v;
+        bfly4(gq[0][k], gq[1][k], gq[2][k], gq[3][k], y0v, y1v, y2v, y3v);
+        contrib[0][k][ly][lx] = y0v;
+        contrib[1][k][ly][lx] = y1v;
+        contrib[2][k][ly][lx] = y2v;
+        contrib[3][k][ly][lx] = y3v;
+      }
+      __syncthreads();
+      if (outv) {
+        T ku[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          ku[k] = (contrib[0][k][ly][lx] + contrib[1][k][ly][lx - 1]) +
+                  (contrib[2][k][ly - 1][lx] + contrib[3][k][ly - 1][lx - 1]);
+        op.store(c, nxy * ez + exy, ex, ey, ez, ku, uown, acc0, acc1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ga[q][k] = wh[q][k] - wh[q + 4][k];
+        tp[q][k] = tn[q][k];
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) uown[k] = unext[k];
+    cur = nxt;
+  }
+  if (Op::NACC > 0) {
+    const double t0 = block_sum<NTHR / 64>(acc0, red);
+    if (tid == 0) op.part.buf[(op.slot0 * 8 + c) * op.part.stride + tile] = t0;
+  }
+  if (Op::NACC > 1) {
+    const double t1 = block_sum<NTHR / 64>(acc1, red);
+    if (tid == 0) op.part.buf[(op.slot1 * 8 + c) * op.part.stride + tile] = t1;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ bool scal_active(const double* scal, int c) {
+  return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
+}
+
+// ------------------------------------------------------------------ ops
+template <typename T>
+struct OpApply {
+  static constexpr int NACC = 0;
+  const T* in;
+  T* out;
+  int64_t n;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
+    return in[(int64_t)(c * 3 + k) * n + i];
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, double&,
+                        double&) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = ku[k];
+  }
+};
+
+// p_new = z + beta p_old (written at owned vertices), q = K p_new, acc p.q
+template <typename T>
+struct OpMatvecP {
+  static constexpr int NACC = 1;
+  const T* z;
+  const T* pold;
+  T* pnew;
+  T* q;
+  int64_t n;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  __device__ T load(int c, int k, int64_t i, int, int, int, bool own) const {
+    const int64_t o = (int64_t)(c * 3 + k) * n + i;
+    const T beta = (T)scal[S_BETA * 8 + c];
+    const T v = z[o] + beta * pold[o];
+    if (own) pnew[o] = v;
+    return v;
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, double& a0,
+                        double&) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      q[(int64_t)(c * 3 + k) * n + i] = ku[k];
+      a0 += (double)uin[k] * (double)ku[k];
+    }
+  }
+};
+
+// t = r - K z0
+template <typename T>
+struct OpResidual {
+  static constexpr int NACC = 0;
+  const T* z0;
+  const T* r;
+  T* t;
+  int64_t n;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
+    return z0[(int64_t)(c * 3 + k) * n + i];
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, double&,
+                        double&) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = (int64_t)(c * 3 + k) * n + i;
+      t[o] = r[o] - ku[k];
+    }
+  }
+};
+
+// z1 = z0 + P ec;  zout = z1 + D^-1 (r - K z1);  acc r.zout
+template <typename T>
+struct OpPostSmooth {
+  static constexpr int NACC = 1;
+  const T* z0;
+  const T* ec;
+  const T* r;
+  const T* dinv;
+  T* zout;
+  int64_t n;
+  Grid gc;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  __device__ T load(int c, int k, int64_t i, int gx, int gy, int gz, bool) const {
+    const int X0 = gx >> 1, Y0 = gy >> 1, Z0 = gz >> 1;
+    const int X1 = (gx & 1) ? (X0 + 1 == gc.nx ? 0 : X0 + 1) : X0;
+    const int Y1 = (gy & 1) ? (Y0 + 1 == gc.ny ? 0 : Y0 + 1) : Y0;
+    const int Z1 = (gz & 1) ? (Z0 + 1 == gc.nz ? 0 : Z0 + 1) : Z0;
+    const T wx = (gx & 1) ? T(0.5) : T(1), wy = (gy & 1) ? T(0.5) : T(1);
+    const T wz = (gz & 1) ? T(0.5) : T(1);
+    const T* e = ec + (int64_t)(c * 3 + k) * gc.n;
+    const int64_t cxy = (int64_t)gc.nx * gc.ny;
+    T v = e[X0 + (int64_t)gc.nx * Y0 + cxy * Z0];
+    if (gx & 1) v += e[X1 + (int64_t)gc.nx * Y0 + cxy * Z0];
+    if (gy & 1) {
+      v += e[X0 + (int64_t)gc.nx * Y1 + cxy * Z0];
+      if (gx & 1) v += e[X1 + (int64_t)gc.nx * Y1 + cxy * Z0];
+    }
+    if (gz & 1) {
+      T w = e[X0 + (int64_t)gc.nx * Y0 + cxy * Z1];
+      if (gx & 1) w += e[X1 + (int64_t)gc.nx * Y0 + cxy * Z1];
+      if (gy & 1) {
+        w += e[X0 + (int64_t)gc.nx * Y1 + cxy * Z1];
+        if (gx & 1) w += e[X1 + (int64_t)gc.nx * Y1 + cxy * Z1];
+      }
+      v += w;
+    }
+    // all taps along an odd axis carry 1/2; the sums above grouped them
+    return z0[(int64_t)(c * 3 + k) * n + i] + wx * wy * wz * v;
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, double& a0,
+                        double&) const {
+    T res[3], rv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      rv[k] = r[(int64_t)(c * 3 + k) * n + i];
+      res[k] = rv[k] - ku[k];
+    }
+    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
+    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
+    T zn[3];
+    zn[0] = uin[0] + (dxx * res[0] + dxy * res[1] + dxz * res[2]);
+    zn[1] = uin[1] + (dxy * res[0] + dyy * res[1] + dyz * res[2]);
+    zn[2] = uin[2] + (dxz * res[0] + dyz * res[1] + dzz * res[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      zout[(int64_t)(c * 3 + k) * n + i] = zn[k];
+      a0 += (double)rv[k] * (double)zn[k];
+    }
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void forcing_at(const Grid& g, const T* __restrict__ s,
+                                           const LoadTpl<T>& tpl, int c, int gx, int gy, int gz,
+                                           T (&f)[3]) {
+  const int xm = gx == 0 ? g.nx - 1 : gx - 1;
+  const int ym = gy == 0 ? g.ny - 1 : gy - 1;
+  const int zm = gz == 0 ? g.nz - 1 : gz - 1;
+  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+  f[0] = f[1] = f[2] = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t e = ((a & 1) ? xm : gx) + nx * ((a & 2) ? ym : gy) + nxy * ((a & 4) ? zm : gz);
+    const T se = s[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] += se * tpl.g[c][a][k];
+  }
+}
+
+// r = f - K x;  acc0 f.f, acc1 r.r
+template <typename T>
+struct OpForceResidual {
+  static constexpr int NACC = 2;
+  const T* x;
+  T* r;
+  const T* s;
+  LoadTpl<T> tpl;
+  Grid g;
+  int64_t n;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
+    return x[(int64_t)(c * 3 + k) * n + i];
+  }
+  __device__ void store(int c, int64_t i, int gx, int gy, int gz, const T* ku, const T*,
+                        double& a0, double& a1) const {
+    T f[3];
+    forcing_at(g, s, tpl, c, gx, gy, gz, f);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T rv = f[k] - ku[k];
+      r[(int64_t)(c * 3 + k) * n + i] = rv;
+      a0 += (double)f[k] * (double)f[k];
+      a1 += (double)rv * (double)rv;
+    }
+  }
+};
+
+template <typename T, class Op>
+void launch_op0(const Op0Launch<T>& L, const Op& op) {
+  const TileGeom tg = tile_geom(L.g);
+  const int nblk = tg.ntiles * NCASE;
+  hipLaunchKernelGGL((op0_kernel<T, Op>), dim3(nblk), dim3(NTHR), 0, L.stream, op, L.g, tg, L.mk,
+                     L.s);
+}
+
+// ------------------------------------------------------------------ pointwise kernels
+template <typename T>
+__global__ void forcing_kernel(Grid g, LoadTpl<T> tpl, const T* __restrict__ s, T* __restrict__ f,
+                               const double* scal, Partials part) {
+  __shared__ double red[4];
+  double acc[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) acc[c] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gx = (int)(i % g.nx);
+    const int gy = (int)((i / g.nx) % g.ny);
+    const int gz = (int)(i / ((int64_t)g.nx * g.ny));
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      T fv[3];
+      forcing_at(g, s, tpl, c, gx, gy, gz, fv);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        f[(int64_t)(c * 3 + k) * g.n + i] = fv[k];
+        acc[c] += (double)fv[k] * (double)fv[k];
+      }
+    }
+  }
+  if (part.buf) {
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      const double t = block_sum<4>(acc[c], red);
+      if (threadIdx.x == 0) part.buf[(S_FF * 8 + c) * part.stride + blockIdx.x] = t;
+    }
+  }
+}
+
+template <typename T>
+__global__ void simp_kernel(int64_t n, const float* __restrict__ rho, T* __restrict__ s,
+                            T* __restrict__ keep, double E0, double Emin, double penal, int* bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double r = rho[i];
+    if (!(r >= 0.0 && r <= 1.0)) {
+      atomicOr(bad, 1);  // any thread; the flag is only tested for nonzero
+      s[i] = T(E0);
+      keep[i] = T(0);
+      continue;
+    }
+    double rp;
+    if (penal == 3.0)
+      rp = r * r * r;
+    else
+      rp = (r > 0.0) ? pow(r, penal) : 0.0;
+    s[i] = (T)(Emin + rp * (E0 - Emin));
+    keep[i] = (T)r;
+  }
+}
+
+// omega * (sum_a s_{v-a} K0[a,a])^-1, stored as xx, yy, zz, xy, yz, xz planes.
+template <typename T>
+__global__ void dinv0_kernel(Grid g, const T* __restrict__ s, double dd, double oo, double omega,
+                             T* __restrict__ dinv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gx = (int)(i % g.nx);
+    const int gy = (int)((i / g.nx) % g.ny);
+    const int gz = (int)(i / ((int64_t)g.nx * g.ny));
+    const int xm = gx == 0 ? g.nx - 1 : gx - 1;
+    const int ym = gy == 0 ? g.ny - 1 : gy - 1;
+    const int zm = gz == 0 ? g.nz - 1 : gz - 1;
+    const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+    double sum = 0.0, sxy = 0.0, syz = 0.0, sxz = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int64_t e = ((a & 1) ? xm : gx) + nx * ((a & 2) ? ym : gy) + nxy * ((a & 4) ? zm : gz);
+      const double se = (double)s[e];
+      const double sx = (a & 1) ? 1.0 : -1.0, sy = (a & 2) ? 1.0 : -1.0;
+      const double sz = (a & 4) ? 1.0 : -1.0;
+      sum += se;
+      sxy += se * sx * sy;
+      syz += se * sy * sz;
+      sxz += se * sx * sz;
+    }
+    const double a00 = dd * sum, a11 = a00, a22 = a00;
+    const double a01 = oo * sxy, a12 = oo * syz, a02 = oo * sxz;
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22;
+    const double c02 = a01 * a12 - a02 * a11, c11 = a00 * a22 - a02 * a02;
+    const double c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    const double f = omega / det;
+    dinv[i] = (T)(f * c00);
+    dinv[g.n + i] = (T)(f * c11);
+    dinv[2 * g.n + i] = (T)(f * c22);
+    dinv[3 * g.n + i] = (T)(f * c01);
+    dinv[4 * g.n + i] = (T)(f * c12);
+    dinv[5 * g.n + i] = (T)(f * c02);
+  }
+}
+
+// 27-point stencil of the level-0 operator: thread per (vertex, offset d).
+template <typename T>
+__global__ void stencil0_kernel(Grid g, const T* __restrict__ s, const double* __restrict__ K0,
+                                T* __restrict__ st) {
+  const int d = blockIdx.y;
+  const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int gx = (int)(i % g.nx);
+    const int gy = (int)((i / g.nx) % g.ny);
+    const int gz = (int)(i / ((int64_t)g.nx * g.ny));
+    double blk[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int a = 0; a < 8; ++a) {
+      const int a0 = a & 1, a1 = (a >> 1) & 1, a2 = a >> 2;
+      const int b0 = a0 + dx, b1 = a1 + dy, b2 = a2 + dz;
+      if (b0 < 0 || b0 > 1 || b1 < 0 || b1 > 1 || b2 < 0 || b2 > 1) continue;
+      const int b = b0 + 2 * b1 + 4 * b2;
+      const int64_t e = modp(gx - a0, g.nx) + (int64_t)g.nx * (modp(gy - a1, g.ny) +
+                        (int64_t)g.ny * modp(gz - a2, g.nz));
+      const double se = (double)s[e];
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) blk[p * 3 + q] += se * K0[(3 * a + p) * 24 + 3 * b + q];
+    }
+    for (int t = 0; t < 9; ++t) st[(int64_t)(d * 9 + t) * g.n + i] = (T)blk[t];
+  }
+}
+
+inline int pw_blocks(int64_t n, int tpb, int cap) {
+  int64_t b = (n + tpb - 1) / tpb;
+  if (b > cap) b = cap;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int op0_blocks_per_case(const Grid& g) { return tile_geom(g).ntiles; }
+
+template <typename T>
+void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal) {
+  OpApply<T> op{in, out, L.g.n, scal, Partials{}, 0, 0};
+  launch_op0(L, op);
+}
+
+template <typename T>
+void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q,
+                  const double* scal, Partials part, int* nblk_out) {
+  // The new direction goes to a separate buffer: the kernel reads halo values of
+  // pold that neighbouring blocks must not have overwritten yet.
+  OpMatvecP<T> op{z, pold, pnew, q, L.g.n, scal, part, S_PQ, 0};
+  launch_op0(L, op);
+  *nblk_out = tile_geom(L.g).ntiles;
+}
+
+template <typename T>
+void op0_residual(const Op0Launch<T>& L, const T* z0, const T* r, T* t, const double* scal) {
+  OpResidual<T> op{z0, r, t, L.g.n, scal, Partials{}, 0, 0};
+  launch_op0(L, op);
+}
+
+template <typename T>
+void op0_post_smooth(const Op0Launch<T>& L, const T* z0, const T* ec, Grid gc, const T* r,
+                     const T* dinv, T* zout, const double* scal, Partials part, int* nblk_out) {
+  OpPostSmooth<T> op{z0, ec, r, dinv, zout, L.g.n, gc, scal, part, S_RZNEW, 0};
+  launch_op0(L, op);
+  *nblk_out = tile_geom(L.g).ntiles;
+}
+
+template <typename T>
+void op0_force_residual(const Op0Launch<T>& L, const LoadTpl<T>& tpl, const T* x, T* r,
+                        const double* scal, Partials part, int* nblk_out) {
+  OpForceResidual<T> op{x, r, L.s, tpl, L.g, L.g.n, scal, part, S_FF, S_TRUE};
+  launch_op0(L, op);
+  *nblk_out = tile_geom(L.g).ntiles;
+}
+
+template <typename T>
+void forcing(const Grid& g, const LoadTpl<T>& tpl, const T* s, T* f, const double* scal,
+             Partials part, int* nblk_out, hipStream_t st) {
+  const int nb = pw_blocks(g.n, 256, part.buf ? part.stride : 4096);
+  hipLaunchKernelGGL(forcing_kernel<T>, dim3(nb), dim3(256), 0, st, g, tpl, s, f, scal, part);
+  if (nblk_out) *nblk_out = nb;
+}
+
+template <typename T>
+void simp_scale(const Grid& g, const float* rho, T* s, T* keep, double E0, double Emin,
+                double penal, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(simp_kernel<T>, dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, st, g.n, rho,
+                     s, keep, E0, Emin, penal, bad);
+}
+
+template <typename T>
+void dinv_level0(const Grid& g, const T* s, double dd, double oo, double omega, T* dinv,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(dinv0_kernel<T>, dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, st, g, s, dd,
+                     oo, omega, dinv);
+}
+
+template <typename T>
+void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipStream_t stm) {
+  hipLaunchKernelGGL(stencil0_kernel<T>, dim3(pw_blocks(g.n, 256, 4096), 27), dim3(256), 0, stm, g,
+                     s, K0_dev, st);
+}
+
+#define HMG_INST(T)                                                                              \
+  template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
+  template void op0_matvec_p<T>(const Op0Launch<T>&, const T*, const T*, T*, T*, const double*, \
+                                Partials, int*);                                                 \
+  template void op0_residual<T>(const Op0Launch<T>&, const T*, const T*, T*, const double*);     \
+  template void op0_post_smooth<T>(const Op0Launch<T>&, const T*, const T*, Grid, const T*,     \
+                                   const T*, T*, const double*, Partials, int*);                 \
+  template void op0_force_residual<T>(const Op0Launch<T>&, const LoadTpl<T>&, const T*, T*,     \
+                                      const double*, Partials, int*);                            \
+  template void forcing<T>(const Grid&, const LoadTpl<T>&, const T*, T*, const double*,         \
+                           Partials, int*, hipStream_t);                                          \
+  template void simp_scale<T>(const Grid&, const float*, T*, T*, double, double, double, int*,   \
+                              hipStream_t);                                                       \
+  template void dinv_level0<T>(const Grid&, const T*, double, double, double, T*, hipStream_t);  \
+  template void stencil_level0<T>(const Grid&, const T*, const double*, T*, hipStream_t);
+HMG_INST(float)
+HMG_INST(double)
+#undef HMG_INST
+
+}  // namespace hmg

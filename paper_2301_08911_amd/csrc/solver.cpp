@@ -1,0 +1,756 @@
+// Host runtime of the solver and the extern "C" entry points of include/hmg.h.
+//
+// One context = one periodic cell on one device.  It owns the multigrid
+// hierarchy (Sec. 3.3) and the PCG work fields, drives the kernels on the
+// caller's HIP stream, and keeps every scalar of the six CG recurrences in
+// FP64 on the device; the host only reads them back once per iteration to
+// decide convergence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hmg.h"
+#include "hmg_internal.hpp"
+
+using namespace hmg;
+
+namespace {
+
+constexpr int MAX_COARSE_DOF = 3072;  // dense inverse of the coarsest grid
+
+struct Status {
+  hmg_status code = HMG_OK;
+  std::string msg;
+};
+
+class DeviceArena {
+ public:
+  ~DeviceArena() { release(); }
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ptrs_.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+  }
+
+ private:
+  std::vector<void*> ptrs_;
+};
+
+// Precision-independent interface of a typed solver.
+class SolverIface {
+ public:
+  virtual ~SolverIface() = default;
+  virtual Status init() = 0;
+  virtual Status set_density(const float* rho) = 0;
+  virtual Status solve(double tol, int max_iter, int init, const void* u0, int iters[6],
+                       double relres[6]) = 0;
+  virtual Status elastic(double C[36]) = 0;
+  virtual Status sens(const double W[36], float* out) = 0;
+  virtual Status get_disp(void* u) = 0;
+  virtual Status apply_op(int level, const void* u, void* y) = 0;
+  virtual Status get_stencil(int level, void* out) = 0;
+  virtual Status loads(void* f) = 0;
+  virtual Status vcycle(const void* r, void* z) = 0;
+  virtual Status transfer(int level, int dir, const void* in, void* out) = 0;
+  virtual int levels() const = 0;
+  virtual Grid level_grid(int l) const = 0;
+};
+
+Status fail(hmg_status code, const char* fmt, ...) {
+  Status s;
+  s.code = code;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  s.msg = buf;
+  return s;
+}
+
+Status check_hip(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HMG_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+  return Status{};
+}
+
+#define HMG_TRY(expr)                        \
+  do {                                       \
+    Status _s = (expr);                      \
+    if (_s.code != HMG_OK) return _s;        \
+  } while (0)
+
+template <typename T>
+class Solver final : public SolverIface {
+ public:
+  Solver(const hmg_config& cfg, hipStream_t st, const ElementConsts& ec, std::vector<Grid> grids)
+      : cfg_(cfg), st_(st), ec_(ec), grids_(std::move(grids)) {}
+
+  int levels() const override { return (int)grids_.size(); }
+  Grid level_grid(int l) const override { return grids_[l]; }
+
+  Status init() override {
+    const Grid& g0 = grids_[0];
+    const int64_t F = (int64_t)NCASE * 3 * g0.n;
+    mk_ = cast_mode(ec_.mk);
+    for (int c = 0; c < NCASE; ++c)
+      for (int a = 0; a < 8; ++a)
+        for (int k = 0; k < 3; ++k) {
+          tpl_.g[c][a][k] = (T)ec_.load[c][a][k];
+          chh_.g[c][a][k] = (T)ec_.chihat[c][a][k];
+        }
+    auto A = [&](size_t bytes) { return arena_.alloc(bytes); };
+    s_ = (T*)A(sizeof(T) * g0.n);
+    rho_ = (T*)A(sizeof(T) * g0.n);
+    dinv0_ = (T*)A(sizeof(T) * 6 * g0.n);
+    x_ = (T*)A(sizeof(T) * F);
+    r_ = (T*)A(sizeof(T) * F);
+    z_ = (T*)A(sizeof(T) * F);
+    t_ = (T*)A(sizeof(T) * F);
+    pa_ = (T*)A(sizeof(T) * F);
+    pb_ = (T*)A(sizeof(T) * F);
+    q_ = (T*)A(sizeof(T) * F);
+    const int L = levels();
+    lev_.resize(L);
+    for (int l = 1; l < L; ++l) {
+      const Grid& g = grids_[l];
+      const int64_t Fl = (int64_t)NCASE * 3 * g.n;
+      lev_[l].st = (T*)A(sizeof(T) * 243 * g.n);
+      lev_[l].dinv = (T*)A(sizeof(T) * 6 * g.n);
+      lev_[l].r = (T*)A(sizeof(T) * Fl);
+      lev_[l].z = (T*)A(sizeof(T) * Fl);
+      lev_[l].t = (T*)A(sizeof(T) * Fl);
+    }
+    const Grid& gL = grids_[L - 1];
+    ncdof_ = (int)(3 * gL.n);
+    Ainv_ = (double*)A(sizeof(double) * ((size_t)ncdof_ * ncdof_ + ncdof_));
+    if (L == 1) st0_ = (T*)A(sizeof(T) * 243 * g0.n);
+    stride_ = std::max(op0_blocks_per_case(g0), 4096);
+    part_.buf = (double*)A(sizeof(double) * (size_t)S_NSLOT * 8 * stride_);
+    part_.stride = stride_;
+    scal_ = (double*)A(sizeof(double) * S_NSLOT * 8);
+    aux_ = (double*)A(sizeof(double) * S_NSLOT * 8);
+    misc_ = (double*)A(sizeof(double) * 64);
+    K0dev_ = (double*)A(sizeof(double) * 576);
+    msig_ = (double*)A(sizeof(double) * 8 * 576);
+    bad_ = (int*)A(sizeof(int) * 4);
+    for (void* p : {(void*)s_, (void*)rho_, (void*)dinv0_, (void*)x_, (void*)r_, (void*)z_,
+                    (void*)t_, (void*)pa_, (void*)pb_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
+                    (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)msig_,
+                    (void*)bad_})
+      if (!p) return fail(HMG_E_OOM, "device allocation failed for a %dx%dx%d cell", g0.nx, g0.ny,
+                          g0.nz);
+    if (L == 1 && !st0_) return fail(HMG_E_OOM, "device allocation failed (level-0 stencil)");
+    for (int l = 1; l < L; ++l)
+      if (!lev_[l].st || !lev_[l].dinv || !lev_[l].r || !lev_[l].z || !lev_[l].t)
+        return fail(HMG_E_OOM, "device allocation failed at level %d", l);
+    if (hipHostMalloc((void**)&hscal_, sizeof(double) * S_NSLOT * 8 * 2) != hipSuccess)
+      return fail(HMG_E_OOM, "pinned host allocation failed");
+    (void)hipMemcpyAsync(K0dev_, &ec_.K0[0][0], sizeof(double) * 576, hipMemcpyHostToDevice, st_);
+    (void)hipMemcpyAsync(msig_, &ec_.msig[0][0][0], sizeof(double) * 8 * 576, hipMemcpyHostToDevice,
+                   st_);
+    vec_fill<T>(x_, F, T(0), st_);
+    HMG_TRY(check_hip("init"));
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("init sync");
+    return Status{};
+  }
+
+  ~Solver() override {
+    if (hscal_) (void)hipHostFree(hscal_);
+  }
+
+  Status set_density(const float* rho) override {
+    const Grid& g0 = grids_[0];
+    (void)hipMemsetAsync(bad_, 0, sizeof(int), st_);
+    simp_scale<T>(g0, rho, s_, rho_, cfg_.E0, cfg_.Emin, cfg_.penal, bad_, st_);
+    int bad = 0;
+    (void)hipMemcpyAsync(&bad, bad_, sizeof(int), hipMemcpyDeviceToHost, st_);
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("set_density");
+    if (bad) return fail(HMG_E_INVALID, "density contains NaN or a value outside [0, 1]");
+    vec_sum_scalar<T>(s_, g0.n, misc_, part_, st_);
+    dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega(), dinv0_, st_);
+    const int L = levels();
+    for (int l = 1; l < L; ++l) {
+      if (l == 1)
+        galerkin_first<T>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
+      else
+        galerkin_next<T>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
+      dinv_from_stencil<T>(grids_[l], lev_[l].st, omega(), lev_[l].dinv, st_);
+    }
+    const T* stc = (L == 1) ? st0_ : lev_[L - 1].st;
+    if (L == 1) stencil_level0<T>(g0, s_, K0dev_, st0_, st_);
+    dense_from_stencil<T>(grids_[L - 1], stc, Ainv_, st_);
+    gauss_jordan_inverse(ncdof_, Ainv_, st_);
+    double ssum = 0.0;
+    (void)hipMemcpyAsync(&ssum, misc_, sizeof(double), hipMemcpyDeviceToHost, st_);
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("set_density assembly");
+    HMG_TRY(check_hip("set_density"));
+    mean_s_ = ssum / (double)g0.n;
+    have_density_ = true;
+    have_solution_ = false;
+    return Status{};
+  }
+
+  Status solve(double tol, int max_iter, int init, const void* u0, int iters[6],
+               double relres[6]) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    if (!(tol > 0.0) || max_iter <= 0 || init < 0 || init > 2 || (init == 2 && !u0))
+      return fail(HMG_E_INVALID, "bad solve arguments (tol %g, max_iter %d, init %d)", tol,
+                  max_iter, init);
+    if (init == 1 && !have_solution_) init = 0;
+    const Grid& g0 = grids_[0];
+    const int64_t F = (int64_t)NCASE * 3 * g0.n;
+    const int64_t cs = 3 * g0.n;
+    Op0Launch<T> L0{g0, mk_, s_, st_};
+    const double lam1 = cfg_.nu / ((1 + cfg_.nu) * (1 - 2 * cfg_.nu));
+    const double mu1 = 1.0 / (2 * (1 + cfg_.nu));
+    const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * mean_s_;
+
+    if (init == 0) vec_fill<T>(x_, F, T(0), st_);
+    if (init == 2) (void)hipMemcpyAsync(x_, u0, sizeof(T) * F, hipMemcpyDeviceToDevice, st_);
+    vec_fill<T>(pa_, F, T(0), st_);
+    scal_set_all_active(scal_, st_);
+    int nb = 0;
+    if (init == 0) {
+      forcing<T>(g0, tpl_, s_, r_, nullptr, part_, &nb, st_);
+      fin_sum(part_, S_FF, nb, scal_, true, st_);
+      (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_FF * 8, sizeof(double) * 8,
+                     hipMemcpyDeviceToDevice, st_);
+    } else {
+      op0_force_residual<T>(L0, tpl_, x_, r_, nullptr, part_, &nb);
+      fin_sum(part_, S_FF, nb, scal_, true, st_);
+      fin_sum(part_, S_TRUE, nb, scal_, true, st_);
+      (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_TRUE * 8, sizeof(double) * 8,
+                     hipMemcpyDeviceToDevice, st_);
+    }
+    fin_init(scal_, eps_abs, tol, st_);
+    HMG_TRY(read_scal(scal_, hscal_));
+    bool active[NCASE];
+    int it_count[NCASE];
+    for (int c = 0; c < NCASE; ++c) {
+      active[c] = hscal_[S_ACTIVE * 8 + c] != 0.0;
+      it_count[c] = 0;
+      if (hscal_[S_TRIVIAL * 8 + c] != 0.0) vec_fill<T>(x_ + c * cs, cs, T(0), st_);
+    }
+    T* pold = pa_;
+    T* pnew = pb_;
+    if (any(active)) {
+      vec_jacobi0<T>(g0, r_, dinv0_, z_, scal_, st_);
+      T* zo = t_;
+      HMG_TRY(vcycle_rest(r_, z_, zo, scal_, &nb));
+      std::swap(z_, t_);
+      fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
+      (void)hipMemcpyAsync(scal_ + S_RZ * 8, scal_ + S_RZNEW * 8, sizeof(double) * 8,
+                     hipMemcpyDeviceToDevice, st_);
+    }
+    int it = 0;
+    while (any(active) && it < max_iter) {
+      ++it;
+      op0_matvec_p<T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
+      fin_sum(part_, S_PQ, nb, scal_, false, st_);
+      fin_alpha(scal_, st_);
+      vec_update_xrz<T>(g0, x_, r_, z_, pnew, q_, dinv0_, scal_, part_, &nb, st_);
+      fin_sum(part_, S_RR, nb, scal_, false, st_);
+      std::swap(pold, pnew);
+      for (int c = 0; c < NCASE; ++c) it_count[c] += active[c] ? 1 : 0;
+      HMG_TRY(read_scal(scal_, hscal_));
+      bool check[NCASE];
+      bool anycheck = false;
+      const bool replace = cfg_.replace_every > 0 && it % cfg_.replace_every == 0;
+      for (int c = 0; c < NCASE; ++c) {
+        check[c] = active[c] && (replace || std::sqrt(hscal_[S_RR * 8 + c]) <=
+                                                hscal_[S_THRESH * 8 + c]);
+        anycheck |= check[c];
+      }
+      if (anycheck) {
+        // Confirm on the recomputed residual f - K x before a case stops; the
+        // recomputed residual also replaces the recursive one.
+        set_mask(aux_, check);
+        op0_force_residual<T>(L0, tpl_, x_, t_, aux_, part_, &nb);
+        fin_sum(part_, S_TRUE, nb, aux_, false, st_);
+        HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+        const double* ha = hscal_ + S_NSLOT * 8;
+        for (int c = 0; c < NCASE; ++c) {
+          if (!check[c]) continue;
+          const double tr = std::sqrt(ha[S_TRUE * 8 + c]);
+          if (tr <= hscal_[S_THRESH * 8 + c]) {
+            active[c] = false;
+          } else {
+            (void)hipMemcpyAsync(r_ + c * cs, t_ + c * cs, sizeof(T) * cs, hipMemcpyDeviceToDevice, st_);
+          }
+        }
+        set_mask(scal_, active);
+        vec_jacobi0<T>(g0, r_, dinv0_, z_, scal_, st_);
+      }
+      if (!any(active)) break;
+      HMG_TRY(vcycle_rest(r_, z_, t_, scal_, &nb));
+      std::swap(z_, t_);
+      fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
+      fin_beta(scal_, st_);
+    }
+    // Zero-mean solution and the recomputed final residual of every case.
+    vec_mean_partial<T>(g0, x_, part_, &nb, st_);
+    fin_mean(part_, nb, g0.n, aux_, st_);
+    vec_mean_subtract<T>(g0, x_, aux_, st_);
+    scal_set_all_active(aux_, st_);
+    op0_force_residual<T>(L0, tpl_, x_, t_, aux_, part_, &nb);
+    fin_sum(part_, S_FF, nb, aux_, true, st_);
+    fin_sum(part_, S_TRUE, nb, aux_, true, st_);
+    HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+    const double* ha = hscal_ + S_NSLOT * 8;
+    for (int c = 0; c < NCASE; ++c) {
+      iters[c] = it_count[c];
+      const bool trivial = hscal_[S_TRIVIAL * 8 + c] != 0.0;
+      const double ff = ha[S_FF * 8 + c];
+      relres[c] = trivial || ff <= 0.0 ? 0.0 : std::sqrt(ha[S_TRUE * 8 + c] / ff);
+    }
+    have_solution_ = true;
+    if (any(active))
+      return fail(HMG_E_NOT_CONVERGED, "max_iter %d reached before rel_tol %g", max_iter, tol);
+    return Status{};
+  }
+
+  Status elastic(double C[36]) override {
+    if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
+    int nb = 0;
+    elastic_partials<T>(grids_[0], mk_, chh_, s_, x_, part_, &nb, st_);
+    elastic_finalize(part_, nb, grids_[0].n, misc_, st_);
+    (void)hipMemcpyAsync(C, misc_, sizeof(double) * 36, hipMemcpyDeviceToHost, st_);
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("elastic_tensor");
+    return check_hip("elastic_tensor");
+  }
+
+  Status sens(const double W[36], float* out) override {
+    if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
+    double w21[21];
+    int t = 0;
+    for (int j = 0; j < NCASE; ++j)
+      for (int i = 0; i <= j; ++i) w21[t++] = (i == j) ? W[i * 6 + i] : W[i * 6 + j] + W[j * 6 + i];
+    (void)hipMemcpyAsync(misc_ + 36, w21, sizeof(double) * 21, hipMemcpyHostToDevice, st_);
+    const double coef = cfg_.penal * (cfg_.E0 - cfg_.Emin) / (double)grids_[0].n;
+    sensitivity<T>(grids_[0], mk_, chh_, rho_, x_, misc_ + 36, coef, cfg_.penal, out, st_);
+    // the host array w21 must outlive the copy
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("sensitivity");
+    return check_hip("sensitivity");
+  }
+
+  Status get_disp(void* u) override {
+    if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
+    (void)hipMemcpyAsync(u, x_, sizeof(T) * NCASE * 3 * grids_[0].n, hipMemcpyDeviceToDevice, st_);
+    return check_hip("get_displacement");
+  }
+
+  Status apply_op(int level, const void* u, void* y) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    if (level == 0) {
+      Op0Launch<T> L0{grids_[0], mk_, s_, st_};
+      op0_apply<T>(L0, (const T*)u, (T*)y, nullptr);
+    } else {
+      kc_apply<T>(grids_[level], lev_[level].st, (const T*)u, (T*)y, st_);
+    }
+    return check_hip("apply_operator");
+  }
+
+  Status get_stencil(int level, void* out) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    if (level == 0)
+      stencil_level0<T>(grids_[0], s_, K0dev_, (T*)out, st_);
+    else
+      (void)hipMemcpyAsync(out, lev_[level].st, sizeof(T) * 243 * grids_[level].n,
+                     hipMemcpyDeviceToDevice, st_);
+    return check_hip("get_stencil");
+  }
+
+  Status loads(void* f) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    forcing<T>(grids_[0], tpl_, s_, (T*)f, nullptr, Partials{}, nullptr, st_);
+    return check_hip("load_vectors");
+  }
+
+  Status vcycle(const void* r, void* z) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    scal_set_all_active(aux_, st_);
+    vec_jacobi0<T>(grids_[0], (const T*)r, dinv0_, z_, aux_, st_);
+    int nb = 0;
+    HMG_TRY(vcycle_rest((const T*)r, z_, (T*)z, aux_, &nb));
+    return check_hip("vcycle");
+  }
+
+  Status transfer(int level, int dir, const void* in, void* out) override {
+    const Grid& gf = grids_[level];
+    const Grid& gc = grids_[level + 1];
+    if (dir == 0)
+      restrict_to<T>(gf, gc, (const T*)in, (T*)out, nullptr, st_);
+    else
+      prolong_add<T>(gf, gc, (T*)out, (const T*)in, nullptr, true, st_);
+    return check_hip("transfer");
+  }
+
+ private:
+  struct Lev {
+    T* st = nullptr;
+    T* dinv = nullptr;
+    T* r = nullptr;
+    T* z = nullptr;
+    T* t = nullptr;
+  };
+
+  static ModeK<T> cast_mode(const ModeK<double>& m) {
+    return ModeK<T>{(T)m.ab, (T)m.b, (T)m.cs, (T)m.p, (T)m.q, (T)m.fg, (T)m.g, (T)m.z};
+  }
+  double omega() const { return cfg_.omega > 0.0 ? cfg_.omega : 0.6; }
+  static bool any(const bool* a) {
+    for (int c = 0; c < NCASE; ++c)
+      if (a[c]) return true;
+    return false;
+  }
+
+  Status read_scal(const double* dev, double* host) {
+    (void)hipMemcpyAsync(host, dev, sizeof(double) * S_NSLOT * 8, hipMemcpyDeviceToHost, st_);
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("scalar readback");
+    return check_hip("scalar readback");
+  }
+
+  void set_mask(double* scal, const bool* on) {
+    double* h = hscal_ + 2 * S_NSLOT * 8 - 8;  // last 8 doubles of the pinned buffer
+    for (int c = 0; c < 8; ++c) h[c] = (c < NCASE && on[c]) ? 1.0 : 0.0;
+    (void)hipMemcpyAsync(scal + S_ACTIVE * 8, h, sizeof(double) * 8, hipMemcpyHostToDevice, st_);
+    (void)hipStreamSynchronize(st_);
+  }
+
+  // Given level-0 r and its pre-smoothed correction z0 = omega D^-1 r, finish
+  // the V-cycle (Alg. 1, with the symmetric post-smoothing) into zout and
+  // leave per-block partials of r . zout in slot S_RZNEW.
+  Status vcycle_rest(const T* r0, const T* z0, T* zout, const double* scal, int* nb) {
+    const int L = levels();
+    const Grid& g0 = grids_[0];
+    if (L == 1) {
+      coarse_solve<T>(g0, Ainv_, r0, zout, scal, st_);
+      vec_dot_cases<T>(g0, r0, zout, scal, part_, S_RZNEW, nb, st_);
+      return check_hip("vcycle");
+    }
+    Op0Launch<T> L0{g0, mk_, s_, st_};
+    op0_residual<T>(L0, z0, r0, t_, scal);
+    restrict_to<T>(g0, grids_[1], t_, lev_[1].r, scal, st_);
+    descend(1, scal);
+    op0_post_smooth<T>(L0, z0, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
+    return check_hip("vcycle");
+  }
+
+  void descend(int l, const double* scal) {
+    const int L = levels();
+    Lev& lv = lev_[l];
+    const Grid& g = grids_[l];
+    if (l == L - 1) {
+      coarse_solve<T>(g, Ainv_, lv.r, lv.z, scal, st_);
+      return;
+    }
+    vec_jacobi0<T>(g, lv.r, lv.dinv, lv.z, scal, st_);
+    kc_residual<T>(g, lv.st, lv.z, lv.r, lv.t, scal, st_);
+    restrict_to<T>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
+    descend(l + 1, scal);
+    prolong_add<T>(g, grids_[l + 1], lv.z, lev_[l + 1].z, scal, false, st_);
+    kc_smooth<T>(g, lv.st, lv.z, lv.r, lv.dinv, lv.t, scal, st_);
+    std::swap(lv.z, lv.t);
+  }
+
+  hmg_config cfg_;
+  hipStream_t st_;
+  ElementConsts ec_;
+  std::vector<Grid> grids_;
+  DeviceArena arena_;
+  ModeK<T> mk_{};
+  LoadTpl<T> tpl_{};
+  LoadTpl<T> chh_{};
+  T *s_ = nullptr, *rho_ = nullptr, *dinv0_ = nullptr;
+  T *x_ = nullptr, *r_ = nullptr, *z_ = nullptr, *t_ = nullptr;
+  T *pa_ = nullptr, *pb_ = nullptr, *q_ = nullptr;
+  T* st0_ = nullptr;
+  std::vector<Lev> lev_;
+  double* Ainv_ = nullptr;
+  int ncdof_ = 0;
+  Partials part_{};
+  int stride_ = 0;
+  double *scal_ = nullptr, *aux_ = nullptr, *misc_ = nullptr;
+  double *K0dev_ = nullptr, *msig_ = nullptr;
+  int* bad_ = nullptr;
+  double* hscal_ = nullptr;
+  double mean_s_ = 1.0;
+  bool have_density_ = false;
+  bool have_solution_ = false;
+};
+
+}  // namespace
+
+struct hmg_ctx_s {
+  hmg_config cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::unique_ptr<SolverIface> solver;
+  Grid g0{};
+  DeviceArena arena;
+  double* ocstate = nullptr;
+  Partials ocpart{};
+  float* fw = nullptr;      // filter weights, (2h+1)^3
+  double fw_radius = -1.0;
+};
+
+namespace {
+
+hmg_status report(hmg_ctx ctx, const Status& s) {
+  if (ctx) ctx->err = s.msg;
+  return s.code;
+}
+
+Status validate(const hmg_config& c, std::vector<Grid>* grids) {
+  if (c.nx < 4 || c.ny < 4 || c.nz < 4)
+    return fail(HMG_E_INVALID, "every axis needs at least 4 cells (got %dx%dx%d)", c.nx, c.ny, c.nz);
+  if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 31)
+    return fail(HMG_E_INVALID, "cell too large");
+  if (!(c.E0 > 0.0) || !(c.nu > -1.0 && c.nu < 0.5) || !(c.penal >= 1.0) || !(c.Emin >= 0.0) ||
+      !(c.Emin < c.E0))
+    return fail(HMG_E_INVALID, "bad material (E0 %g, nu %g, penal %g, Emin %g)", c.E0, c.nu,
+                c.penal, c.Emin);
+  if (c.omega < 0.0 || c.omega >= 1.0) return fail(HMG_E_INVALID, "omega must be in [0, 1)");
+  if ((c.nu_pre != 0 && c.nu_pre != 1) || (c.nu_post != 0 && c.nu_post != 1))
+    return fail(HMG_E_INVALID, "only one pre- and one post-smoothing sweep are supported");
+  if (c.precision != HMG_FP64 && c.precision != HMG_FP32)
+    return fail(HMG_E_INVALID, "precision %d is not built in this library", c.precision);
+  if (c.levels < 0 || c.replace_every < 0) return fail(HMG_E_INVALID, "bad levels/replace_every");
+  grids->clear();
+  Grid g{c.nx, c.ny, c.nz, (int64_t)c.nx * c.ny * c.nz};
+  grids->push_back(g);
+  while (true) {
+    if (c.levels > 0 && (int)grids->size() == c.levels) break;
+    const Grid& f = grids->back();
+    if (f.nx % 2 || f.ny % 2 || f.nz % 2 || f.nx / 2 < 4 || f.ny / 2 < 4 || f.nz / 2 < 4) break;
+    Grid h{f.nx / 2, f.ny / 2, f.nz / 2, (int64_t)(f.nx / 2) * (f.ny / 2) * (f.nz / 2)};
+    grids->push_back(h);
+  }
+  if (c.levels > 0 && (int)grids->size() != c.levels)
+    return fail(HMG_E_INVALID, "cannot build %d levels on a %dx%dx%d cell", c.levels, c.nx, c.ny,
+                c.nz);
+  const int64_t ndof = 3 * grids->back().n;
+  if (ndof > MAX_COARSE_DOF)
+    return fail(HMG_E_INVALID, "coarsest grid has %lld unknowns; the direct solver takes at most %d",
+                (long long)ndof, MAX_COARSE_DOF);
+  return Status{};
+}
+
+}  // namespace
+
+extern "C" {
+
+hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out) {
+  if (!cfg || !out) return HMG_E_INVALID;
+  *out = nullptr;
+  std::vector<Grid> grids;
+  Status s = validate(*cfg, &grids);
+  if (s.code != HMG_OK) {
+    std::fprintf(stderr, "hmg_create: %s\n", s.msg.c_str());
+    return s.code;
+  }
+  ElementConsts* ec = new ElementConsts;
+  char err[256] = {0};
+  if (build_element_consts(cfg->nu, ec, err, sizeof(err)) != 0) {
+    std::fprintf(stderr, "hmg_create: %s\n", err);
+    delete ec;
+    return HMG_E_INVALID;
+  }
+  hmg_ctx ctx = new hmg_ctx_s;
+  ctx->cfg = *cfg;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->g0 = grids[0];
+  if (cfg->precision == HMG_FP64)
+    ctx->solver.reset(new Solver<double>(*cfg, ctx->stream, *ec, grids));
+  else
+    ctx->solver.reset(new Solver<float>(*cfg, ctx->stream, *ec, grids));
+  delete ec;
+  s = ctx->solver->init();
+  if (s.code == HMG_OK) {
+    ctx->ocstate = (double*)ctx->arena.alloc(sizeof(double) * 8);
+    ctx->ocpart.buf = (double*)ctx->arena.alloc(sizeof(double) * 4096);
+    ctx->ocpart.stride = 4096;
+    if (!ctx->ocstate || !ctx->ocpart.buf) s = fail(HMG_E_OOM, "device allocation failed");
+  }
+  if (s.code != HMG_OK) {
+    std::fprintf(stderr, "hmg_create: %s\n", s.msg.c_str());
+    delete ctx;
+    return s.code;
+  }
+  *out = ctx;
+  return HMG_OK;
+}
+
+hmg_status hmg_destroy(hmg_ctx ctx) {
+  if (!ctx) return HMG_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return HMG_OK;
+}
+
+hmg_status hmg_set_density(hmg_ctx ctx, const float* rho_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!rho_dev) return report(ctx, fail(HMG_E_INVALID, "rho_dev is NULL"));
+  return report(ctx, ctx->solver->set_density(rho_dev));
+}
+
+hmg_status hmg_solve_cases(hmg_ctx ctx, double rel_tol, int32_t max_iter, int32_t init,
+                           const void* u0_dev, int32_t iters_out[6], double relres_out[6]) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!iters_out || !relres_out) return report(ctx, fail(HMG_E_INVALID, "NULL host output"));
+  int it[6];
+  double rr[6];
+  Status s = ctx->solver->solve(rel_tol, max_iter, init, u0_dev, it, rr);
+  if (s.code == HMG_OK || s.code == HMG_E_NOT_CONVERGED)
+    for (int c = 0; c < 6; ++c) {
+      iters_out[c] = it[c];
+      relres_out[c] = rr[c];
+    }
+  return report(ctx, s);
+}
+
+hmg_status hmg_elastic_tensor(hmg_ctx ctx, double C_out[36]) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!C_out) return report(ctx, fail(HMG_E_INVALID, "C_out is NULL"));
+  return report(ctx, ctx->solver->elastic(C_out));
+}
+
+hmg_status hmg_sensitivity(hmg_ctx ctx, const double W[36], float* dfdrho_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!W || !dfdrho_dev) return report(ctx, fail(HMG_E_INVALID, "NULL argument"));
+  return report(ctx, ctx->solver->sens(W, dfdrho_dev));
+}
+
+hmg_status hmg_oc_update(hmg_ctx ctx, float* x_dev, const float* dfdx_dev, double volfrac,
+                         double move, double damp, double xmin, double* lambda_out) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!x_dev || !dfdx_dev) return report(ctx, fail(HMG_E_INVALID, "NULL argument"));
+  if (!(volfrac > 0.0 && volfrac <= 1.0) || !(move > 0.0) || !(damp > 0.0) ||
+      !(xmin >= 0.0 && xmin < 1.0))
+    return report(ctx, fail(HMG_E_INVALID, "bad OC parameters"));
+  hipStream_t st = ctx->stream;
+  oc_init(ctx->ocstate, st);
+  int nb = 0;
+  for (int k = 0; k < 200; ++k) {
+    oc_partial(ctx->g0, x_dev, dfdx_dev, move, damp, xmin, ctx->ocstate, ctx->ocpart, &nb, st);
+    oc_step(ctx->ocpart, nb, ctx->g0.n, volfrac, ctx->ocstate, st);
+  }
+  oc_apply(ctx->g0, x_dev, dfdx_dev, move, damp, xmin, ctx->ocstate, st);
+  double state[4];
+  (void)hipMemcpyAsync(state, ctx->ocstate, sizeof(double) * 4, hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return report(ctx, check_hip("oc_update"));
+  if (lambda_out) *lambda_out = state[3];
+  return report(ctx, check_hip("oc_update"));
+}
+
+hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double radius,
+                      int32_t adjoint) {
+  (void)adjoint;  // the cone filter is symmetric: H^T = H
+  if (!ctx) return HMG_E_INVALID;
+  if (!in_dev || !out_dev || in_dev == out_dev)
+    return report(ctx, fail(HMG_E_INVALID, "filter needs distinct non-NULL buffers"));
+  if (!(radius > 1.0 && radius <= 4.0))
+    return report(ctx, fail(HMG_E_INVALID, "radius must be in (1, 4]"));
+  const int h = (int)std::ceil(radius) - 1;
+  if (radius != ctx->fw_radius) {
+    const int span = 2 * h + 1;
+    std::vector<float> w((size_t)span * span * span);
+    double sum = 0.0;
+    std::vector<double> wd(w.size());
+    int t = 0;
+    for (int dz = -h; dz <= h; ++dz)
+      for (int dy = -h; dy <= h; ++dy)
+        for (int dx = -h; dx <= h; ++dx, ++t) {
+          const double v = radius - std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+          wd[t] = v > 0.0 ? v : 0.0;
+          sum += wd[t];
+        }
+    for (size_t i = 0; i < w.size(); ++i) w[i] = (float)(wd[i] / sum);
+    if (!ctx->fw) ctx->fw = (float*)ctx->arena.alloc(sizeof(float) * 7 * 7 * 7);
+    if (!ctx->fw) return report(ctx, fail(HMG_E_OOM, "device allocation failed"));
+    (void)hipMemcpy(ctx->fw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+    ctx->fw_radius = radius;
+  }
+  density_filter(ctx->g0, in_dev, out_dev, ctx->fw, h, ctx->stream);
+  return report(ctx, check_hip("filter"));
+}
+
+hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!u_dev) return report(ctx, fail(HMG_E_INVALID, "u_dev is NULL"));
+  return report(ctx, ctx->solver->get_disp(u_dev));
+}
+
+const char* hmg_last_error(hmg_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+hmg_status hmg_num_levels(hmg_ctx ctx, int32_t* levels_out) {
+  if (!ctx || !levels_out) return HMG_E_INVALID;
+  *levels_out = ctx->solver->levels();
+  return HMG_OK;
+}
+
+hmg_status hmg_level_dims(hmg_ctx ctx, int32_t level, int32_t dims_out[3]) {
+  if (!ctx || !dims_out) return HMG_E_INVALID;
+  if (level < 0 || level >= ctx->solver->levels())
+    return report(ctx, fail(HMG_E_INVALID, "level %d out of range", level));
+  const Grid g = ctx->solver->level_grid(level);
+  dims_out[0] = g.nx;
+  dims_out[1] = g.ny;
+  dims_out[2] = g.nz;
+  return HMG_OK;
+}
+
+hmg_status hmg_apply_operator(hmg_ctx ctx, int32_t level, const void* u_dev, void* y_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (level < 0 || level >= ctx->solver->levels() || !u_dev || !y_dev || u_dev == y_dev)
+    return report(ctx, fail(HMG_E_INVALID, "bad apply_operator arguments"));
+  return report(ctx, ctx->solver->apply_op(level, u_dev, y_dev));
+}
+
+hmg_status hmg_get_stencil(hmg_ctx ctx, int32_t level, void* out_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (level < 0 || level >= ctx->solver->levels() || !out_dev)
+    return report(ctx, fail(HMG_E_INVALID, "bad get_stencil arguments"));
+  return report(ctx, ctx->solver->get_stencil(level, out_dev));
+}
+
+hmg_status hmg_load_vectors(hmg_ctx ctx, void* f_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!f_dev) return report(ctx, fail(HMG_E_INVALID, "f_dev is NULL"));
+  return report(ctx, ctx->solver->loads(f_dev));
+}
+
+hmg_status hmg_vcycle(hmg_ctx ctx, const void* r_dev, void* z_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!r_dev || !z_dev || r_dev == z_dev)
+    return report(ctx, fail(HMG_E_INVALID, "bad vcycle arguments"));
+  return report(ctx, ctx->solver->vcycle(r_dev, z_dev));
+}
+
+hmg_status hmg_transfer(hmg_ctx ctx, int32_t level, int32_t direction, const void* in_dev,
+                        void* out_dev) {
+  if (!ctx) return HMG_E_INVALID;
+  if (level < 0 || level + 1 >= ctx->solver->levels() || (direction != 0 && direction != 1) ||
+      !in_dev || !out_dev || in_dev == out_dev)
+    return report(ctx, fail(HMG_E_INVALID, "bad transfer arguments"));
+  return report(ctx, ctx->solver->transfer(level, direction, in_dev, out_dev));
+}
+
+}  // extern "C"

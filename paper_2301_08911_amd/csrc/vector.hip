@@ -1,0 +1,353 @@
+// Pointwise PCG kernels on the fine grid and the small finalizer kernels that
+// turn deterministic per-block partial sums into the FP64 scalars of the six
+// CG recurrences (dot products, step lengths, convergence state).
+#include "hmg_internal.hpp"
+
+namespace hmg {
+namespace {
+
+constexpr int VB = 256;       // threads per block of the pointwise kernels
+constexpr int VCAP = 4096;    // cap on their grid (grid-stride loops)
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NW; ++i) s += lds[i];
+  return s;
+}
+
+__device__ __forceinline__ bool case_on(const double* scal, int c) {
+  return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
+}
+
+// x += alpha p; r -= alpha q; z0 = Dinv r; partial ||r||^2.
+template <typename T>
+__global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
+                                                    T* __restrict__ z0, const T* __restrict__ p,
+                                                    const T* __restrict__ q,
+                                                    const T* __restrict__ dinv, const double* scal,
+                                                    Partials part) {
+  __shared__ double red[VB / 64];
+  bool on[NCASE];
+  T al[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) {
+    on[c] = case_on(scal, c);
+    al[c] = (T)scal[S_ALPHA * 8 + c];
+  }
+  double acc[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) acc[c] = 0.0;
+  const int64_t n = g.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
+    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      if (!on[c]) continue;
+      T rv[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t o = (int64_t)(c * 3 + k) * n + i;
+        x[o] = x[o] + al[c] * p[o];
+        rv[k] = r[o] - al[c] * q[o];
+        r[o] = rv[k];
+        acc[c] += (double)rv[k] * (double)rv[k];
+      }
+      z0[(int64_t)(c * 3 + 0) * n + i] = dxx * rv[0] + dxy * rv[1] + dxz * rv[2];
+      z0[(int64_t)(c * 3 + 1) * n + i] = dxy * rv[0] + dyy * rv[1] + dyz * rv[2];
+      z0[(int64_t)(c * 3 + 2) * n + i] = dxz * rv[0] + dyz * rv[1] + dzz * rv[2];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) {
+    const double t = block_sum<VB / 64>(acc[c], red);
+    if (threadIdx.x == 0) part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const T* __restrict__ r,
+                                                     const T* __restrict__ dinv, T* __restrict__ z,
+                                                     const double* scal) {
+  bool on[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  const int64_t n = g.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
+    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      if (!on[c]) continue;
+      const T r0 = r[(int64_t)(c * 3 + 0) * n + i], r1 = r[(int64_t)(c * 3 + 1) * n + i];
+      const T r2 = r[(int64_t)(c * 3 + 2) * n + i];
+      z[(int64_t)(c * 3 + 0) * n + i] = dxx * r0 + dxy * r1 + dxz * r2;
+      z[(int64_t)(c * 3 + 1) * n + i] = dxy * r0 + dyy * r1 + dyz * r2;
+      z[(int64_t)(c * 3 + 2) * n + i] = dxz * r0 + dyz * r1 + dzz * r2;
+    }
+  }
+}
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ a, int64_t count, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+template <typename T>
+__global__ void copy_kernel(T* __restrict__ d, const T* __restrict__ s, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VB) dot_kernel(Grid g, const T* __restrict__ a,
+                                                 const T* __restrict__ b, const double* scal,
+                                                 Partials part, int slot) {
+  __shared__ double red[VB / 64];
+  double acc[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) acc[c] = 0.0;
+  const int64_t n = g.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      if (!case_on(scal, c)) continue;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t o = (int64_t)(c * 3 + k) * n + i;
+        acc[c] += (double)a[o] * (double)b[o];
+      }
+    }
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) {
+    const double t = block_sum<VB / 64>(acc[c], red);
+    if (threadIdx.x == 0) part.buf[(slot * 8 + c) * part.stride + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VB) mean_partial_kernel(Grid g, const T* __restrict__ a,
+                                                          Partials part) {
+  __shared__ double red[VB / 64];
+  const int64_t n = g.n;
+  for (int ck = 0; ck < NCASE * 3; ++ck) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+      acc += (double)a[(int64_t)ck * n + i];
+    const double t = block_sum<VB / 64>(acc, red);
+    const int c = ck / 3, k = ck % 3;
+    if (threadIdx.x == 0) part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = t;
+  }
+}
+
+template <typename T>
+__global__ void mean_subtract_kernel(Grid g, T* __restrict__ a, const double* scal) {
+  const int64_t n = g.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t o = (int64_t)(c * 3 + k) * n + i;
+        a[o] = a[o] - (T)scal[(S_MEAN0 + k) * 8 + c];
+      }
+}
+
+// ---------------------------------------------------------------- finalizers
+// One block per case; fixed summation order, so results are reproducible.
+__global__ void __launch_bounds__(256) fin_sum_kernel(Partials part, int slot, int nblk,
+                                                      double* scal, int all) {
+  __shared__ double red[4];
+  const int c = blockIdx.x;
+  if (!all && scal[S_ACTIVE * 8 + c] == 0.0) return;
+  double a = 0.0;
+  const double* src = part.buf + (int64_t)(slot * 8 + c) * part.stride;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) a += src[i];
+  const double t = block_sum<4>(a, red);
+  if (threadIdx.x == 0) scal[slot * 8 + c] = t;
+}
+
+__global__ void fin_init_kernel(double* scal, double eps_abs, double tol) {
+  const int c = threadIdx.x;
+  if (c >= NCASE) return;
+  const double fn = sqrt(scal[S_FF * 8 + c]);
+  const double rn = sqrt(scal[S_RR * 8 + c]);
+  const bool trivial = fn <= eps_abs;
+  const double th = fmax(tol * fn, eps_abs);
+  scal[S_TRIVIAL * 8 + c] = trivial ? 1.0 : 0.0;
+  scal[S_THRESH * 8 + c] = th;
+  scal[S_ACTIVE * 8 + c] = (!trivial && rn > th) ? 1.0 : 0.0;
+  scal[S_ALPHA * 8 + c] = 0.0;
+  scal[S_BETA * 8 + c] = 0.0;
+  scal[S_RZ * 8 + c] = 0.0;
+}
+
+__global__ void fin_alpha_kernel(double* scal) {
+  const int c = threadIdx.x;
+  if (c >= NCASE) return;
+  const double pq = scal[S_PQ * 8 + c];
+  const bool on = scal[S_ACTIVE * 8 + c] != 0.0 && pq != 0.0;
+  scal[S_ALPHA * 8 + c] = on ? scal[S_RZ * 8 + c] / pq : 0.0;
+}
+
+__global__ void fin_beta_kernel(double* scal) {
+  const int c = threadIdx.x;
+  if (c >= NCASE) return;
+  if (scal[S_ACTIVE * 8 + c] == 0.0) return;
+  const double rz = scal[S_RZ * 8 + c], rzn = scal[S_RZNEW * 8 + c];
+  scal[S_BETA * 8 + c] = rz != 0.0 ? rzn / rz : 0.0;
+  scal[S_RZ * 8 + c] = rzn;
+}
+
+__global__ void fin_mean_kernel(Partials part, int nblk, int64_t n, double* scal) {
+  __shared__ double red[4];
+  const int c = blockIdx.x % NCASE, k = blockIdx.x / NCASE;
+  double a = 0.0;
+  const double* src = part.buf + (int64_t)((S_MEAN0 + k) * 8 + c) * part.stride;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) a += src[i];
+  const double t = block_sum<4>(a, red);
+  if (threadIdx.x == 0) scal[(S_MEAN0 + k) * 8 + c] = t / (double)n;
+}
+
+__global__ void all_active_kernel(double* scal) {
+  const int c = threadIdx.x;
+  if (c < 8) {
+    scal[S_ACTIVE * 8 + c] = 1.0;
+    scal[S_BETA * 8 + c] = 0.0;
+    scal[S_ALPHA * 8 + c] = 0.0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(VB) sum_kernel(const T* __restrict__ a, int64_t n, Partials part) {
+  __shared__ double red[VB / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)a[i];
+  const double t = block_sum<VB / 64>(acc, red);
+  if (threadIdx.x == 0) part.buf[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) sum_fin_kernel(Partials part, int nblk, double* out) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) a += part.buf[i];
+  const double t = block_sum<4>(a, red);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+inline int blocks_for(int64_t n) {
+  int64_t b = (n + VB - 1) / VB;
+  if (b > VCAP) b = VCAP;
+  return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+int vec_blocks(const Grid& g) { return blocks_for(g.n); }
+
+template <typename T>
+void vec_update_xrz(const Grid& g, T* x, T* r, T* z0, const T* p, const T* q, const T* dinv,
+                    const double* scal, Partials part, int* nblk_out, hipStream_t st) {
+  const int nb = blocks_for(g.n);
+  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, x, r, z0, p, q, dinv, scal,
+                     part);
+  *nblk_out = nb;
+}
+template <typename T>
+void vec_jacobi0(const Grid& g, const T* r, const T* dinv, T* z, const double* scal,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, r, dinv, z,
+                     scal);
+}
+template <typename T>
+void vec_fill(T* a, int64_t count, T v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count, v);
+}
+template <typename T>
+void vec_copy(T* d, const T* s, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(copy_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, d, s, count);
+}
+template <typename T>
+void vec_dot_cases(const Grid& g, const T* a, const T* b, const double* scal, Partials part,
+                   int slot, int* nblk_out, hipStream_t st) {
+  const int nb = blocks_for(g.n);
+  hipLaunchKernelGGL(dot_kernel<T>, dim3(nb), dim3(VB), 0, st, g, a, b, scal, part, slot);
+  *nblk_out = nb;
+}
+template <typename T>
+void vec_mean_partial(const Grid& g, const T* a, Partials part, int* nblk_out, hipStream_t st) {
+  const int nb = blocks_for(g.n);
+  hipLaunchKernelGGL(mean_partial_kernel<T>, dim3(nb), dim3(VB), 0, st, g, a, part);
+  *nblk_out = nb;
+}
+template <typename T>
+void vec_mean_subtract(const Grid& g, T* a, const double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(mean_subtract_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, a, scal);
+}
+
+template <typename T>
+void vec_sum_scalar(const T* a, int64_t n, double* out_dev, Partials part, hipStream_t st) {
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(sum_kernel<T>, dim3(nb), dim3(VB), 0, st, a, n, part);
+  hipLaunchKernelGGL(sum_fin_kernel, dim3(1), dim3(256), 0, st, part, nb, out_dev);
+}
+
+void fin_sum(const Partials& part, int slot, int nblk, double* scal, bool all_cases,
+             hipStream_t st) {
+  hipLaunchKernelGGL(fin_sum_kernel, dim3(NCASE), dim3(256), 0, st, part, slot, nblk, scal,
+                     all_cases ? 1 : 0);
+}
+void fin_init(double* scal, double eps_abs, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(fin_init_kernel, dim3(1), dim3(64), 0, st, scal, eps_abs, tol);
+}
+void fin_alpha(double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(fin_alpha_kernel, dim3(1), dim3(64), 0, st, scal);
+}
+void fin_beta(double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(fin_beta_kernel, dim3(1), dim3(64), 0, st, scal);
+}
+void fin_mean(const Partials& part, int nblk, int64_t n, double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(fin_mean_kernel, dim3(NCASE * 3), dim3(256), 0, st, part, nblk, n, scal);
+}
+void scal_set_all_active(double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(all_active_kernel, dim3(1), dim3(64), 0, st, scal);
+}
+
+#define HMG_INST(T)                                                                             \
+  template void vec_update_xrz<T>(const Grid&, T*, T*, T*, const T*, const T*, const T*,        \
+                                  const double*, Partials, int*, hipStream_t);                  \
+  template void vec_jacobi0<T>(const Grid&, const T*, const T*, T*, const double*, hipStream_t); \
+  template void vec_fill<T>(T*, int64_t, T, hipStream_t);                                       \
+  template void vec_copy<T>(T*, const T*, int64_t, hipStream_t);                                \
+  template void vec_dot_cases<T>(const Grid&, const T*, const T*, const double*, Partials, int,  \
+                                 int*, hipStream_t);                                            \
+  template void vec_mean_partial<T>(const Grid&, const T*, Partials, int*, hipStream_t);        \
+  template void vec_mean_subtract<T>(const Grid&, T*, const double*, hipStream_t);        \
+  template void vec_sum_scalar<T>(const T*, int64_t, double*, Partials, hipStream_t);
+HMG_INST(float)
+HMG_INST(double)
+#undef HMG_INST
+
+}  // namespace hmg

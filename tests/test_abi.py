@@ -1,0 +1,62 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmg.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for core in ("hmg_set_density", "hmg_solve_cases", "hmg_elastic_tensor", "hmg_sensitivity",
+                 "hmg_oc_update"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2301_08911_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libhmg.so is not built; run python -m paper_2301_08911_amd.build")
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(_lib.SYMBOLS) == set(declared_symbols())
+
+
+def test_config_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of hmg_config has the C compiler's size and offsets."""
+    import shutil
+    import subprocess
+    from paper_2301_08911_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in _lib.HmgConfig._fields_]
+    prog = tmp_path / "layout.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\nint main(void){\n'
+                    'printf("%%zu", sizeof(hmg_config));\n%s\nreturn 0;}\n' % (
+                        HEADER, "".join('printf(" %%zu", offsetof(hmg_config, %s));' % f
+                                        for f in fields)))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(prog), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(_lib.HmgConfig)
+    assert out[1:] == [getattr(_lib.HmgConfig, f).offset for f in fields]
+
+
+def test_no_fallback_when_library_missing(tmp_path, monkeypatch):
+    from paper_2301_08911_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
