@@ -76,7 +76,7 @@ typedef struct hmg_config {
   int32_t levels;         /* multigrid levels; 0 = coarsen 1:2 while every
                              axis stays even and the coarse mesh is >= 4 per
                              axis (Sec. 3.3)                                   */
-  double omega;           /* damped block-Jacobi weight; 0 selects 0.6         */
+  double omega;           /* block-Jacobi damping; 0 = per level 1.6/lambda_l  */
   int32_t nu_pre;         /* pre-smoothing sweeps; only 1 is supported          */
   int32_t nu_post;        /* post-smoothing sweeps; only 1 is supported         */
   int32_t precision;      /* hmg_precision                                     */
@@ -160,6 +160,13 @@ const char* hmg_last_error(hmg_ctx ctx);
 /* Number of multigrid levels and the cells per axis of one level. */
 hmg_status hmg_num_levels(hmg_ctx ctx, int32_t* levels_out);
 hmg_status hmg_level_dims(hmg_ctx ctx, int32_t level, int32_t dims_out[3]);
+
+/* Block-Jacobi damping used on a level after the last hmg_set_density:
+ * 1.6 / lambda_l, with lambda_l a bound of the spectrum of D_l^-1 K_l (level 0:
+ * the element bound, valid for any densities; coarser levels: power
+ * iteration + 5 %).  A configured omega replaces 1.6/lambda_l but is capped at
+ * 1.9/lambda_l.  0 for the coarsest level, which is solved directly. */
+hmg_status hmg_level_omega(hmg_ctx ctx, int32_t level, double* omega_out);
 
 /* y = K_l u for the six cases on one level (field type, case-major SoA at that
  * level's size).  Level 0 is the matrix-free operator of Sec. 4.2

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhmg.so")
 SYMBOLS = (
     "hmg_create", "hmg_destroy", "hmg_set_density", "hmg_solve_cases", "hmg_elastic_tensor",
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
-    "hmg_num_levels", "hmg_level_dims", "hmg_apply_operator", "hmg_get_stencil",
+    "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
     "hmg_load_vectors", "hmg_vcycle", "hmg_transfer",
 )
 
@@ -53,6 +53,7 @@ def load() -> ctypes.CDLL:
         "hmg_last_error": ([vp], ctypes.c_char_p),
         "hmg_num_levels": ([vp, P(i32)], i32),
         "hmg_level_dims": ([vp, i32, P(i32)], i32),
+        "hmg_level_omega": ([vp, i32, P(f64)], i32),
         "hmg_apply_operator": ([vp, i32, vp, vp], i32),
         "hmg_get_stencil": ([vp, i32, vp], i32),
         "hmg_load_vectors": ([vp, vp], i32),

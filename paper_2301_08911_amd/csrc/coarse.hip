@@ -29,11 +29,12 @@ __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
 
-// MODE 0: out = K u.  MODE 1: out = r - K u.  MODE 2: out = u + Dinv (r - K u).
+// MODE 0: out = K u.  MODE 1: out = (r - m) - K u.  MODE 2: out = u + Dinv ((r - m) - K u).
+// m is the per-component mean of r (slots S_MEAN* of `mean`, FP64).
 template <typename T, int MODE>
 __global__ void stencil_kernel(Grid g, const T* __restrict__ st, const T* __restrict__ u,
                                const T* __restrict__ r, const T* __restrict__ dinv,
-                               T* __restrict__ out, const double* scal) {
+                               T* __restrict__ out, const double* scal, const double* mean) {
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
@@ -80,7 +81,9 @@ __global__ void stencil_kernel(Grid g, const T* __restrict__ st, const T* __rest
       } else {
         T res[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) res[k] = r[(int64_t)(c * 3 + k) * n + i] - acc[c][k];
+        for (int k = 0; k < 3; ++k)
+          res[k] = (T)((double)r[(int64_t)(c * 3 + k) * n + i] - mean[(S_MEAN0 + k) * 8 + c]) -
+                   acc[c][k];
         if (MODE == 1) {
 #pragma unroll
           for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = res[k];
@@ -388,19 +391,20 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
 template <typename T>
 void kc_apply(const Grid& g, const T* st, const T* u, T* y, hipStream_t s) {
   hipLaunchKernelGGL((stencil_kernel<T, 0>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, u, (const T*)nullptr, (const T*)nullptr, y, (const double*)nullptr);
+                     st, u, (const T*)nullptr, (const T*)nullptr, y, (const double*)nullptr,
+                     (const double*)nullptr);
 }
 template <typename T>
 void kc_residual(const Grid& g, const T* st, const T* z, const T* r, T* t, const double* scal,
-                 hipStream_t s) {
+                 const double* mean, hipStream_t s) {
   hipLaunchKernelGGL((stencil_kernel<T, 1>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, z, r, (const T*)nullptr, t, scal);
+                     st, z, r, (const T*)nullptr, t, scal, mean);
 }
 template <typename T>
 void kc_smooth(const Grid& g, const T* st, const T* z, const T* r, const T* dinv, T* zout,
-               const double* scal, hipStream_t s) {
+               const double* scal, const double* mean, hipStream_t s) {
   hipLaunchKernelGGL((stencil_kernel<T, 2>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, z, r, dinv, zout, scal);
+                     st, z, r, dinv, zout, scal, mean);
 }
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
@@ -450,9 +454,9 @@ void coarse_solve(const Grid& g, const double* Ainv, const T* r, T* z, const dou
 #define HMG_INST(T)                                                                               \
   template void kc_apply<T>(const Grid&, const T*, const T*, T*, hipStream_t);                    \
   template void kc_residual<T>(const Grid&, const T*, const T*, const T*, T*, const double*,      \
-                               hipStream_t);                                                        \
+                               const double*, hipStream_t);                                         \
   template void kc_smooth<T>(const Grid&, const T*, const T*, const T*, const T*, T*,             \
-                             const double*, hipStream_t);                                           \
+                             const double*, const double*, hipStream_t);                            \
   template void restrict_to<T>(const Grid&, const Grid&, const T*, T*, const double*, hipStream_t); \
   template void prolong_add<T>(const Grid&, const Grid&, T*, const T*, const double*, bool,       \
                                hipStream_t);                                                        \

@@ -152,6 +152,61 @@ int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen
         }
       }
 
+  // ---- spectral bound of block Jacobi on one element: largest eigenvalue of
+  // blockdiag(K0)^-1 K0, by power iteration (24 unknowns, run to convergence).
+  // Since K = sum_e s_e Q_e^T K0 Q_e and D = sum_e s_e blockdiag(K0 placed at e),
+  // lambda_max(D^-1 K) <= lam0 for every density field.
+  {
+    double Dinv[8][3][3];
+    for (int a = 0; a < 8; ++a) {
+      double m[3][3];
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) m[p][q] = out->K0[3 * a + p][3 * a + q];
+      const double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+      const double c01 = m[0][2] * m[2][1] - m[0][1] * m[2][2];
+      const double c02 = m[0][1] * m[1][2] - m[0][2] * m[1][1];
+      const double c10 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+      const double c11 = m[0][0] * m[2][2] - m[0][2] * m[2][0];
+      const double c12 = m[0][2] * m[1][0] - m[0][0] * m[1][2];
+      const double c20 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+      const double c21 = m[0][1] * m[2][0] - m[0][0] * m[2][1];
+      const double c22 = m[0][0] * m[1][1] - m[0][1] * m[1][0];
+      const double det = m[0][0] * c00 + m[0][1] * c10 + m[0][2] * c20;
+      const double inv[3][3] = {{c00, c01, c02}, {c10, c11, c12}, {c20, c21, c22}};
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) Dinv[a][p][q] = inv[p][q] / det;
+    }
+    double x[24], y[24];
+    for (int i = 0; i < 24; ++i) x[i] = 1.0 + 0.37 * i - 0.011 * i * i;
+    double lam = 0.0;
+    for (int it = 0; it < 20000; ++it) {
+      for (int i = 0; i < 24; ++i) {
+        y[i] = 0.0;
+        for (int j = 0; j < 24; ++j) y[i] += out->K0[i][j] * x[j];
+      }
+      double num = 0.0, den = 0.0;  // Rayleigh quotient x^T K0 x / x^T D x
+      for (int i = 0; i < 24; ++i) num += x[i] * y[i];
+      double z[24];
+      for (int a = 0; a < 8; ++a)
+        for (int p = 0; p < 3; ++p) {
+          z[3 * a + p] = 0.0;
+          for (int q = 0; q < 3; ++q) z[3 * a + p] += Dinv[a][p][q] * y[3 * a + q];
+        }
+      for (int a = 0; a < 8; ++a)
+        for (int p = 0; p < 3; ++p) {
+          double dx = 0.0;
+          for (int q = 0; q < 3; ++q) dx += out->K0[3 * a + p][3 * a + q] * x[3 * a + q];
+          den += x[3 * a + p] * dx;
+        }
+      lam = num / den;
+      double nrm = 0.0;
+      for (int i = 0; i < 24; ++i) nrm += z[i] * z[i];
+      nrm = std::sqrt(nrm);
+      for (int i = 0; i < 24; ++i) x[i] = z[i] / nrm;
+    }
+    out->lam0 = lam;
+  }
+
   // ---- sub-element Galerkin matrices: fine element at sub-position sigma of
   // a coarse element; its node b sits at xi = (sigma + b)/2 in coarse-element
   // coordinates and takes trilinear weights of the coarse nodes A.

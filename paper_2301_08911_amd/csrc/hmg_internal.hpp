@@ -46,6 +46,8 @@ struct ElementConsts {
   double chihat[NCASE][8][3]; // H chi^i (mode basis)
   double dd, oo;              // K0[a,a] = dd I + oo * sg_p sg_q (p != q), sg = +-1 by node bit
   double msig[8][24][24];     // W_sigma^T K0 W_sigma for the 8 sub-element positions
+  double lam0;                // max eigenvalue of blockdiag(K0)^-1 K0: bounds the level-0
+                              // block-Jacobi spectrum for any densities
 };
 
 // Returns 0 on success; fills `err` otherwise.
@@ -67,6 +69,7 @@ enum Slot {
   S_MEAN1,
   S_MEAN2,
   S_TRUE,       // recomputed ||f - K x||^2
+  S_RESTART,    // 1: the residual was just recomputed; restart the direction (beta = 0)
   S_NSLOT
 };
 
@@ -89,22 +92,28 @@ void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal);
 template <typename T>
 void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q,
                   const double* scal, Partials part, int* nblk_out);
+// z0 = Dinv (r - m) (also written out) and t = (r - m) - K z0; m from scal S_MEAN*.
 template <typename T>
-void op0_residual(const Op0Launch<T>& L, const T* z0, const T* r, T* t, const double* scal);
+void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
+                  const double* scal);
+// z1 = z0 + P ec; zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW.
 template <typename T>
 void op0_post_smooth(const Op0Launch<T>& L, const T* z0, const T* ec, Grid gc, const T* r,
                      const T* dinv, T* zout, const double* scal, Partials part, int* nblk_out);
-template <typename T>
-void op0_force_residual(const Op0Launch<T>& L, const LoadTpl<T>& tpl, const T* x, T* r,
-                        const double* scal, Partials part, int* nblk_out);
+// r = f - K x evaluated in FP64 (x, s and the constants in double), stored as R.
+template <typename R>
+void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
+                        R* r, const double* scal, Partials part, int* nblk_out);
 int op0_blocks_per_case(const Grid& g);
 
+// Macro-strain loads evaluated in FP64, stored as R; partial ||f||^2 in S_FF.
+template <typename R>
+void forcing(const Grid& g, const LoadTpl<double>& tpl, const double* s, R* f, Partials part,
+             int* nblk_out, hipStream_t st);
+// s = Emin + rho^p (E0 - Emin) as T (and optionally in double), rho kept as T / double.
 template <typename T>
-void forcing(const Grid& g, const LoadTpl<T>& tpl, const T* s, T* f, const double* scal,
-             Partials part, int* nblk_out, hipStream_t st);
-template <typename T>
-void simp_scale(const Grid& g, const float* rho, T* s, T* rho_keep, double E0, double Emin,
-                double penal, int* bad, hipStream_t st);
+void simp_scale(const Grid& g, const float* rho, T* s, T* rho_keep, double* s64, double* rho64,
+                double E0, double Emin, double penal, int* bad, hipStream_t st);
 template <typename T>
 void dinv_level0(const Grid& g, const T* s, double dd, double oo, double omega, T* dinv,
                  hipStream_t st);
@@ -112,14 +121,21 @@ template <typename T>
 void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipStream_t stm);
 
 // ---------------------------------------------------------------- vectors
+// x (FP64) += alpha p; r -= alpha q; partials ||r||^2 (S_RR) and sum r (S_MEAN*).
 template <typename T>
-void vec_update_xrz(const Grid& g, T* x, T* r, T* z0, const T* p, const T* q, const T* dinv,
-                    const double* scal, Partials part, int* nblk_out, hipStream_t st);
+void vec_update_xr(const Grid& g, double* x, T* r, const T* p, const T* q, const double* scal,
+                   Partials part, int* nblk_out, hipStream_t st);
+template <typename S, typename D>
+void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);
+// z = Dinv (r - m) with m from `mean` slots S_MEAN* (NULL: no shift).
 template <typename T>
 void vec_jacobi0(const Grid& g, const T* r, const T* dinv, T* z, const double* scal,
-                 hipStream_t st);
+                 const double* mean, hipStream_t st);
 template <typename T>
 void vec_fill(T* a, int64_t count, T v, hipStream_t st);
+// Deterministic pseudo-random values in [-1, 1) (power-iteration start vectors).
+template <typename T>
+void vec_pattern(T* a, int64_t count, hipStream_t st);
 template <typename T>
 void vec_copy(T* dst, const T* src, int64_t count, hipStream_t st);
 template <typename T>
@@ -148,10 +164,10 @@ template <typename T>
 void kc_apply(const Grid& g, const T* st, const T* u, T* y, hipStream_t s);
 template <typename T>
 void kc_residual(const Grid& g, const T* st, const T* z, const T* r, T* t, const double* scal,
-                 hipStream_t s);
+                 const double* mean, hipStream_t s);
 template <typename T>
 void kc_smooth(const Grid& g, const T* st, const T* z, const T* r, const T* dinv, T* zout,
-               const double* scal, hipStream_t s);
+               const double* scal, const double* mean, hipStream_t s);
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s);

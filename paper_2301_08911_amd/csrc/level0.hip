@@ -315,27 +315,42 @@ struct OpMatvecP {
   }
 };
 
-// t = r - K z0
+// Pre-smoothing from zero and residual: z0 = Dinv (r - m) (formed while the
+// plane is staged, written at owned vertices), t = (r - m) - K z0.  m is the
+// per-component mean of r (FP64), removed before Dinv so that rounding-level
+// translation components of r are not amplified in soft regions.
 template <typename T>
 struct OpResidual {
   static constexpr int NACC = 0;
-  const T* z0;
   const T* r;
+  const T* dinv;
+  T* z0;
   T* t;
   int64_t n;
   const double* scal;
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
-    return z0[(int64_t)(c * 3 + k) * n + i];
+  __device__ T load(int c, int k, int64_t i, int, int, int, bool own) const {
+    const double r0 = (double)r[(int64_t)(c * 3 + 0) * n + i] - scal[S_MEAN0 * 8 + c];
+    const double r1 = (double)r[(int64_t)(c * 3 + 1) * n + i] - scal[S_MEAN1 * 8 + c];
+    const double r2 = (double)r[(int64_t)(c * 3 + 2) * n + i] - scal[S_MEAN2 * 8 + c];
+    // dinv planes: xx, yy, zz, xy, yz, xz
+    const int a = k, b = (k + 1) % 3, d = (k + 2) % 3;
+    const double daa = (double)dinv[(int64_t)a * n + i];
+    const double dab = (double)dinv[(int64_t)(k == 0 ? 3 : (k == 1 ? 4 : 5)) * n + i];
+    const double dad = (double)dinv[(int64_t)(k == 0 ? 5 : (k == 1 ? 3 : 4)) * n + i];
+    const double rv[3] = {r0, r1, r2};
+    const T v = (T)(daa * rv[a] + dab * rv[b] + dad * rv[d]);
+    if (own) z0[(int64_t)(c * 3 + k) * n + i] = v;
+    return v;
   }
   __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, double&,
                         double&) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t o = (int64_t)(c * 3 + k) * n + i;
-      t[o] = r[o] - ku[k];
+      t[o] = (T)((double)r[o] - scal[(S_MEAN0 + k) * 8 + c]) - ku[k];
     }
   }
 };
@@ -387,7 +402,7 @@ struct OpPostSmooth {
     T res[3], rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      rv[k] = r[(int64_t)(c * 3 + k) * n + i];
+      rv[k] = (T)((double)r[(int64_t)(c * 3 + k) * n + i] - scal[(S_MEAN0 + k) * 8 + c]);
       res[k] = rv[k] - ku[k];
     }
     const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
@@ -422,12 +437,12 @@ __device__ __forceinline__ void forcing_at(const Grid& g, const T* __restrict__ 
   }
 }
 
-// r = f - K x;  acc0 f.f, acc1 r.r
-template <typename T>
+// r = f - K x (computed in T, stored as R);  acc0 f.f, acc1 r.r
+template <typename T, typename R>
 struct OpForceResidual {
   static constexpr int NACC = 2;
   const T* x;
-  T* r;
+  R* r;
   const T* s;
   LoadTpl<T> tpl;
   Grid g;
@@ -446,7 +461,7 @@ struct OpForceResidual {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const T rv = f[k] - ku[k];
-      r[(int64_t)(c * 3 + k) * n + i] = rv;
+      r[(int64_t)(c * 3 + k) * n + i] = (R)rv;
       a0 += (double)f[k] * (double)f[k];
       a1 += (double)rv * (double)rv;
     }
@@ -462,9 +477,9 @@ void launch_op0(const Op0Launch<T>& L, const Op& op) {
 }
 
 // ------------------------------------------------------------------ pointwise kernels
-template <typename T>
-__global__ void forcing_kernel(Grid g, LoadTpl<T> tpl, const T* __restrict__ s, T* __restrict__ f,
-                               const double* scal, Partials part) {
+template <typename R>
+__global__ void forcing_kernel(Grid g, LoadTpl<double> tpl, const double* __restrict__ s,
+                               R* __restrict__ f, Partials part) {
   __shared__ double red[4];
   double acc[NCASE];
 #pragma unroll
@@ -476,12 +491,12 @@ __global__ void forcing_kernel(Grid g, LoadTpl<T> tpl, const T* __restrict__ s, 
     const int gz = (int)(i / ((int64_t)g.nx * g.ny));
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
-      T fv[3];
+      double fv[3];
       forcing_at(g, s, tpl, c, gx, gy, gz, fv);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        f[(int64_t)(c * 3 + k) * g.n + i] = fv[k];
-        acc[c] += (double)fv[k] * (double)fv[k];
+        f[(int64_t)(c * 3 + k) * g.n + i] = (R)fv[k];
+        acc[c] += fv[k] * fv[k];
       }
     }
   }
@@ -496,7 +511,9 @@ __global__ void forcing_kernel(Grid g, LoadTpl<T> tpl, const T* __restrict__ s, 
 
 template <typename T>
 __global__ void simp_kernel(int64_t n, const float* __restrict__ rho, T* __restrict__ s,
-                            T* __restrict__ keep, double E0, double Emin, double penal, int* bad) {
+                            T* __restrict__ keep, double* __restrict__ s64,
+                            double* __restrict__ keep64, double E0, double Emin, double penal,
+                            int* bad) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double r = rho[i];
@@ -504,6 +521,10 @@ __global__ void simp_kernel(int64_t n, const float* __restrict__ rho, T* __restr
       atomicOr(bad, 1);  // any thread; the flag is only tested for nonzero
       s[i] = T(E0);
       keep[i] = T(0);
+      if (s64) {
+        s64[i] = E0;
+        keep64[i] = 0.0;
+      }
       continue;
     }
     double rp;
@@ -511,8 +532,13 @@ __global__ void simp_kernel(int64_t n, const float* __restrict__ rho, T* __restr
       rp = r * r * r;
     else
       rp = (r > 0.0) ? pow(r, penal) : 0.0;
-    s[i] = (T)(Emin + rp * (E0 - Emin));
+    const double sv = Emin + rp * (E0 - Emin);
+    s[i] = (T)sv;
     keep[i] = (T)r;
+    if (s64) {
+      s64[i] = sv;
+      keep64[i] = r;
+    }
   }
 }
 
@@ -611,8 +637,9 @@ void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* 
 }
 
 template <typename T>
-void op0_residual(const Op0Launch<T>& L, const T* z0, const T* r, T* t, const double* scal) {
-  OpResidual<T> op{z0, r, t, L.g.n, scal, Partials{}, 0, 0};
+void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
+                  const double* scal) {
+  OpResidual<T> op{r, dinv, z0, t, L.g.n, scal, Partials{}, 0, 0};
   launch_op0(L, op);
 }
 
@@ -624,27 +651,27 @@ void op0_post_smooth(const Op0Launch<T>& L, const T* z0, const T* ec, Grid gc, c
   *nblk_out = tile_geom(L.g).ntiles;
 }
 
-template <typename T>
-void op0_force_residual(const Op0Launch<T>& L, const LoadTpl<T>& tpl, const T* x, T* r,
-                        const double* scal, Partials part, int* nblk_out) {
-  OpForceResidual<T> op{x, r, L.s, tpl, L.g, L.g.n, scal, part, S_FF, S_TRUE};
+template <typename R>
+void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
+                        R* r, const double* scal, Partials part, int* nblk_out) {
+  OpForceResidual<double, R> op{x, r, L.s, tpl, L.g, L.g.n, scal, part, S_FF, S_TRUE};
   launch_op0(L, op);
   *nblk_out = tile_geom(L.g).ntiles;
 }
 
-template <typename T>
-void forcing(const Grid& g, const LoadTpl<T>& tpl, const T* s, T* f, const double* scal,
-             Partials part, int* nblk_out, hipStream_t st) {
+template <typename R>
+void forcing(const Grid& g, const LoadTpl<double>& tpl, const double* s, R* f, Partials part,
+             int* nblk_out, hipStream_t st) {
   const int nb = pw_blocks(g.n, 256, part.buf ? part.stride : 4096);
-  hipLaunchKernelGGL(forcing_kernel<T>, dim3(nb), dim3(256), 0, st, g, tpl, s, f, scal, part);
+  hipLaunchKernelGGL(forcing_kernel<R>, dim3(nb), dim3(256), 0, st, g, tpl, s, f, part);
   if (nblk_out) *nblk_out = nb;
 }
 
 template <typename T>
-void simp_scale(const Grid& g, const float* rho, T* s, T* keep, double E0, double Emin,
-                double penal, int* bad, hipStream_t st) {
+void simp_scale(const Grid& g, const float* rho, T* s, T* keep, double* s64, double* keep64,
+                double E0, double Emin, double penal, int* bad, hipStream_t st) {
   hipLaunchKernelGGL(simp_kernel<T>, dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, st, g.n, rho,
-                     s, keep, E0, Emin, penal, bad);
+                     s, keep, s64, keep64, E0, Emin, penal, bad);
 }
 
 template <typename T>
@@ -664,15 +691,16 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
   template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
   template void op0_matvec_p<T>(const Op0Launch<T>&, const T*, const T*, T*, T*, const double*, \
                                 Partials, int*);                                                 \
-  template void op0_residual<T>(const Op0Launch<T>&, const T*, const T*, T*, const double*);     \
+  template void op0_residual<T>(const Op0Launch<T>&, const T*, const T*, T*, T*,               \
+                                const double*);                                                  \
   template void op0_post_smooth<T>(const Op0Launch<T>&, const T*, const T*, Grid, const T*,     \
                                    const T*, T*, const double*, Partials, int*);                 \
-  template void op0_force_residual<T>(const Op0Launch<T>&, const LoadTpl<T>&, const T*, T*,     \
-                                      const double*, Partials, int*);                            \
-  template void forcing<T>(const Grid&, const LoadTpl<T>&, const T*, T*, const double*,         \
-                           Partials, int*, hipStream_t);                                          \
-  template void simp_scale<T>(const Grid&, const float*, T*, T*, double, double, double, int*,   \
-                              hipStream_t);                                                       \
+  template void op0_force_residual<T>(const Op0Launch<double>&, const LoadTpl<double>&,         \
+                                      const double*, T*, const double*, Partials, int*);         \
+  template void forcing<T>(const Grid&, const LoadTpl<double>&, const double*, T*, Partials,    \
+                           int*, hipStream_t);                                                    \
+  template void simp_scale<T>(const Grid&, const float*, T*, T*, double*, double*, double,       \
+                              double, double, int*, hipStream_t);                                 \
   template void dinv_level0<T>(const Grid&, const T*, double, double, double, T*, hipStream_t);  \
   template void stencil_level0<T>(const Grid&, const T*, const double*, T*, hipStream_t);
 HMG_INST(float)

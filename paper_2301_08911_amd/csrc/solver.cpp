@@ -70,6 +70,7 @@ class SolverIface {
   virtual Status transfer(int level, int dir, const void* in, void* out) = 0;
   virtual int levels() const = 0;
   virtual Grid level_grid(int l) const = 0;
+  virtual double level_omega(int l) const = 0;
 };
 
 Status fail(hmg_status code, const char* fmt, ...) {
@@ -104,22 +105,34 @@ class Solver final : public SolverIface {
 
   int levels() const override { return (int)grids_.size(); }
   Grid level_grid(int l) const override { return grids_[l]; }
+  double level_omega(int l) const override {
+    return l < (int)omega_.size() ? omega_[l] : 0.0;
+  }
 
   Status init() override {
     const Grid& g0 = grids_[0];
     const int64_t F = (int64_t)NCASE * 3 * g0.n;
     mk_ = cast_mode(ec_.mk);
+    mk64_ = ec_.mk;
     for (int c = 0; c < NCASE; ++c)
       for (int a = 0; a < 8; ++a)
         for (int k = 0; k < 3; ++k) {
           tpl_.g[c][a][k] = (T)ec_.load[c][a][k];
-          chh_.g[c][a][k] = (T)ec_.chihat[c][a][k];
+          tpl64_.g[c][a][k] = ec_.load[c][a][k];
+          chh64_.g[c][a][k] = ec_.chihat[c][a][k];
         }
     auto A = [&](size_t bytes) { return arena_.alloc(bytes); };
     s_ = (T*)A(sizeof(T) * g0.n);
     rho_ = (T*)A(sizeof(T) * g0.n);
     dinv0_ = (T*)A(sizeof(T) * 6 * g0.n);
-    x_ = (T*)A(sizeof(T) * F);
+    x_ = (double*)A(sizeof(double) * F);
+    if (sizeof(T) == sizeof(double)) {
+      s64_ = (double*)s_;
+      rho64_ = (double*)rho_;
+    } else {
+      s64_ = (double*)A(sizeof(double) * g0.n);
+      rho64_ = (double*)A(sizeof(double) * g0.n);
+    }
     r_ = (T*)A(sizeof(T) * F);
     z_ = (T*)A(sizeof(T) * F);
     t_ = (T*)A(sizeof(T) * F);
@@ -136,6 +149,7 @@ class Solver final : public SolverIface {
       lev_[l].r = (T*)A(sizeof(T) * Fl);
       lev_[l].z = (T*)A(sizeof(T) * Fl);
       lev_[l].t = (T*)A(sizeof(T) * Fl);
+      lev_[l].ms = (double*)A(sizeof(double) * S_NSLOT * 8);
     }
     const Grid& gL = grids_[L - 1];
     ncdof_ = (int)(3 * gL.n);
@@ -153,19 +167,20 @@ class Solver final : public SolverIface {
     for (void* p : {(void*)s_, (void*)rho_, (void*)dinv0_, (void*)x_, (void*)r_, (void*)z_,
                     (void*)t_, (void*)pa_, (void*)pb_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
                     (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)msig_,
-                    (void*)bad_})
+                    (void*)bad_, (void*)s64_, (void*)rho64_})
       if (!p) return fail(HMG_E_OOM, "device allocation failed for a %dx%dx%d cell", g0.nx, g0.ny,
                           g0.nz);
     if (L == 1 && !st0_) return fail(HMG_E_OOM, "device allocation failed (level-0 stencil)");
     for (int l = 1; l < L; ++l)
-      if (!lev_[l].st || !lev_[l].dinv || !lev_[l].r || !lev_[l].z || !lev_[l].t)
+      if (!lev_[l].st || !lev_[l].dinv || !lev_[l].r || !lev_[l].z || !lev_[l].t || !lev_[l].ms)
         return fail(HMG_E_OOM, "device allocation failed at level %d", l);
-    if (hipHostMalloc((void**)&hscal_, sizeof(double) * S_NSLOT * 8 * 2) != hipSuccess)
+    if (hipHostMalloc((void**)&hscal_, sizeof(double) * S_NSLOT * 8 * 3) != hipSuccess)
       return fail(HMG_E_OOM, "pinned host allocation failed");
+    hstage_ = hscal_ + 2 * S_NSLOT * 8;
     (void)hipMemcpyAsync(K0dev_, &ec_.K0[0][0], sizeof(double) * 576, hipMemcpyHostToDevice, st_);
     (void)hipMemcpyAsync(msig_, &ec_.msig[0][0][0], sizeof(double) * 8 * 576, hipMemcpyHostToDevice,
                    st_);
-    vec_fill<T>(x_, F, T(0), st_);
+    vec_fill<double>(x_, F, 0.0, st_);
     HMG_TRY(check_hip("init"));
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("init sync");
     return Status{};
@@ -178,20 +193,32 @@ class Solver final : public SolverIface {
   Status set_density(const float* rho) override {
     const Grid& g0 = grids_[0];
     (void)hipMemsetAsync(bad_, 0, sizeof(int), st_);
-    simp_scale<T>(g0, rho, s_, rho_, cfg_.E0, cfg_.Emin, cfg_.penal, bad_, st_);
+    const bool sep = sizeof(T) != sizeof(double);
+    simp_scale<T>(g0, rho, s_, rho_, sep ? s64_ : nullptr, sep ? rho64_ : nullptr, cfg_.E0,
+                  cfg_.Emin, cfg_.penal, bad_, st_);
     int bad = 0;
     (void)hipMemcpyAsync(&bad, bad_, sizeof(int), hipMemcpyDeviceToHost, st_);
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("set_density");
     if (bad) return fail(HMG_E_INVALID, "density contains NaN or a value outside [0, 1]");
     vec_sum_scalar<T>(s_, g0.n, misc_, part_, st_);
-    dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega(), dinv0_, st_);
     const int L = levels();
+    omega_.assign(L, 0.0);
+    lambda_.assign(L, 0.0);
+    lambda_[0] = ec_.lam0;
+    omega_[0] = omega_for(ec_.lam0);
+    dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
     for (int l = 1; l < L; ++l) {
       if (l == 1)
         galerkin_first<T>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
       else
         galerkin_next<T>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
-      dinv_from_stencil<T>(grids_[l], lev_[l].st, omega(), lev_[l].dinv, st_);
+      if (l == L - 1) continue;  // the coarsest level is solved directly
+      dinv_from_stencil<T>(grids_[l], lev_[l].st, 1.0, lev_[l].dinv, st_);
+      double lam = 0.0;
+      HMG_TRY(estimate_lambda(l, &lam));
+      lambda_[l] = lam;
+      omega_[l] = omega_for(lam);
+      dinv_from_stencil<T>(grids_[l], lev_[l].st, omega_[l], lev_[l].dinv, st_);
     }
     const T* stc = (L == 1) ? st0_ : lev_[L - 1].st;
     if (L == 1) stencil_level0<T>(g0, s_, K0dev_, st0_, st_);
@@ -218,46 +245,47 @@ class Solver final : public SolverIface {
     const int64_t F = (int64_t)NCASE * 3 * g0.n;
     const int64_t cs = 3 * g0.n;
     Op0Launch<T> L0{g0, mk_, s_, st_};
+    Op0Launch<double> L64{g0, mk64_, s64_, st_};
     const double lam1 = cfg_.nu / ((1 + cfg_.nu) * (1 - 2 * cfg_.nu));
     const double mu1 = 1.0 / (2 * (1 + cfg_.nu));
     const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * mean_s_;
 
-    if (init == 0) vec_fill<T>(x_, F, T(0), st_);
-    if (init == 2) (void)hipMemcpyAsync(x_, u0, sizeof(T) * F, hipMemcpyDeviceToDevice, st_);
+    if (init == 0) vec_fill<double>(x_, F, 0.0, st_);
+    if (init == 2) vec_convert<T, double>(x_, (const T*)u0, F, st_);
     vec_fill<T>(pa_, F, T(0), st_);
     scal_set_all_active(scal_, st_);
     int nb = 0;
+    // r = f - K x with f and K x in FP64 (f alone for a zero start).
     if (init == 0) {
-      forcing<T>(g0, tpl_, s_, r_, nullptr, part_, &nb, st_);
+      forcing<T>(g0, tpl64_, s64_, r_, part_, &nb, st_);
       fin_sum(part_, S_FF, nb, scal_, true, st_);
       (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_FF * 8, sizeof(double) * 8,
-                     hipMemcpyDeviceToDevice, st_);
+                           hipMemcpyDeviceToDevice, st_);
     } else {
-      op0_force_residual<T>(L0, tpl_, x_, r_, nullptr, part_, &nb);
+      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
       fin_sum(part_, S_FF, nb, scal_, true, st_);
       fin_sum(part_, S_TRUE, nb, scal_, true, st_);
       (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_TRUE * 8, sizeof(double) * 8,
-                     hipMemcpyDeviceToDevice, st_);
+                           hipMemcpyDeviceToDevice, st_);
     }
+    residual_mean(scal_);
     fin_init(scal_, eps_abs, tol, st_);
     HMG_TRY(read_scal(scal_, hscal_));
     bool active[NCASE];
     int it_count[NCASE];
     for (int c = 0; c < NCASE; ++c) {
       active[c] = hscal_[S_ACTIVE * 8 + c] != 0.0;
+      last_true_[c] = std::sqrt(hscal_[S_RR * 8 + c]);
       it_count[c] = 0;
-      if (hscal_[S_TRIVIAL * 8 + c] != 0.0) vec_fill<T>(x_ + c * cs, cs, T(0), st_);
+      if (hscal_[S_TRIVIAL * 8 + c] != 0.0) vec_fill<double>(x_ + c * cs, cs, 0.0, st_);
     }
     T* pold = pa_;
     T* pnew = pb_;
     if (any(active)) {
-      vec_jacobi0<T>(g0, r_, dinv0_, z_, scal_, st_);
-      T* zo = t_;
-      HMG_TRY(vcycle_rest(r_, z_, zo, scal_, &nb));
-      std::swap(z_, t_);
+      HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
       (void)hipMemcpyAsync(scal_ + S_RZ * 8, scal_ + S_RZNEW * 8, sizeof(double) * 8,
-                     hipMemcpyDeviceToDevice, st_);
+                           hipMemcpyDeviceToDevice, st_);
     }
     int it = 0;
     while (any(active) && it < max_iter) {
@@ -265,8 +293,9 @@ class Solver final : public SolverIface {
       op0_matvec_p<T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      vec_update_xrz<T>(g0, x_, r_, z_, pnew, q_, dinv0_, scal_, part_, &nb, st_);
+      vec_update_xr<T>(g0, x_, r_, pnew, q_, scal_, part_, &nb, st_);
       fin_sum(part_, S_RR, nb, scal_, false, st_);
+      fin_mean(part_, nb, g0.n, scal_, st_);
       std::swap(pold, pnew);
       for (int c = 0; c < NCASE; ++c) it_count[c] += active[c] ? 1 : 0;
       HMG_TRY(read_scal(scal_, hscal_));
@@ -274,42 +303,51 @@ class Solver final : public SolverIface {
       bool anycheck = false;
       const bool replace = cfg_.replace_every > 0 && it % cfg_.replace_every == 0;
       for (int c = 0; c < NCASE; ++c) {
-        check[c] = active[c] && (replace || std::sqrt(hscal_[S_RR * 8 + c]) <=
-                                                hscal_[S_THRESH * 8 + c]);
+        const double rn = std::sqrt(hscal_[S_RR * 8 + c]);
+        // recompute when the recursive residual claims convergence, every
+        // replace_every iterations, or once it has dropped 100x below the last
+        // recomputed one (low-precision recursions drift from f - K x)
+        check[c] = active[c] && (replace || rn <= hscal_[S_THRESH * 8 + c] ||
+                                 rn <= 1e-2 * last_true_[c]);
         anycheck |= check[c];
       }
       if (anycheck) {
-        // Confirm on the recomputed residual f - K x before a case stops; the
-        // recomputed residual also replaces the recursive one.
+        // Confirm on the residual f - K x recomputed in FP64 before a case
+        // stops; the recomputed residual also replaces the recursive one.
         set_mask(aux_, check);
-        op0_force_residual<T>(L0, tpl_, x_, t_, aux_, part_, &nb);
+        op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb);
         fin_sum(part_, S_TRUE, nb, aux_, false, st_);
         HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
         const double* ha = hscal_ + S_NSLOT * 8;
+        bool restart[NCASE];
         for (int c = 0; c < NCASE; ++c) {
+          restart[c] = false;
           if (!check[c]) continue;
           const double tr = std::sqrt(ha[S_TRUE * 8 + c]);
+          last_true_[c] = tr;
           if (tr <= hscal_[S_THRESH * 8 + c]) {
             active[c] = false;
           } else {
-            (void)hipMemcpyAsync(r_ + c * cs, t_ + c * cs, sizeof(T) * cs, hipMemcpyDeviceToDevice, st_);
+            (void)hipMemcpyAsync(r_ + c * cs, t_ + c * cs, sizeof(T) * cs, hipMemcpyDeviceToDevice,
+                                 st_);
+            restart[c] = true;
           }
         }
         set_mask(scal_, active);
-        vec_jacobi0<T>(g0, r_, dinv0_, z_, scal_, st_);
+        set_slot(scal_, S_RESTART, restart);
+        residual_mean(scal_);
       }
       if (!any(active)) break;
-      HMG_TRY(vcycle_rest(r_, z_, t_, scal_, &nb));
-      std::swap(z_, t_);
+      HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
       fin_beta(scal_, st_);
     }
     // Zero-mean solution and the recomputed final residual of every case.
-    vec_mean_partial<T>(g0, x_, part_, &nb, st_);
+    vec_mean_partial<double>(g0, x_, part_, &nb, st_);
     fin_mean(part_, nb, g0.n, aux_, st_);
-    vec_mean_subtract<T>(g0, x_, aux_, st_);
+    vec_mean_subtract<double>(g0, x_, aux_, st_);
     scal_set_all_active(aux_, st_);
-    op0_force_residual<T>(L0, tpl_, x_, t_, aux_, part_, &nb);
+    op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb);
     fin_sum(part_, S_FF, nb, aux_, true, st_);
     fin_sum(part_, S_TRUE, nb, aux_, true, st_);
     HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
@@ -329,7 +367,7 @@ class Solver final : public SolverIface {
   Status elastic(double C[36]) override {
     if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
     int nb = 0;
-    elastic_partials<T>(grids_[0], mk_, chh_, s_, x_, part_, &nb, st_);
+    elastic_partials<double>(grids_[0], mk64_, chh64_, s64_, x_, part_, &nb, st_);
     elastic_finalize(part_, nb, grids_[0].n, misc_, st_);
     (void)hipMemcpyAsync(C, misc_, sizeof(double) * 36, hipMemcpyDeviceToHost, st_);
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("elastic_tensor");
@@ -344,7 +382,8 @@ class Solver final : public SolverIface {
       for (int i = 0; i <= j; ++i) w21[t++] = (i == j) ? W[i * 6 + i] : W[i * 6 + j] + W[j * 6 + i];
     (void)hipMemcpyAsync(misc_ + 36, w21, sizeof(double) * 21, hipMemcpyHostToDevice, st_);
     const double coef = cfg_.penal * (cfg_.E0 - cfg_.Emin) / (double)grids_[0].n;
-    sensitivity<T>(grids_[0], mk_, chh_, rho_, x_, misc_ + 36, coef, cfg_.penal, out, st_);
+    sensitivity<double>(grids_[0], mk64_, chh64_, rho64_, x_, misc_ + 36, coef, cfg_.penal, out,
+                        st_);
     // the host array w21 must outlive the copy
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("sensitivity");
     return check_hip("sensitivity");
@@ -352,7 +391,7 @@ class Solver final : public SolverIface {
 
   Status get_disp(void* u) override {
     if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
-    (void)hipMemcpyAsync(u, x_, sizeof(T) * NCASE * 3 * grids_[0].n, hipMemcpyDeviceToDevice, st_);
+    vec_convert<double, T>((T*)u, x_, (int64_t)NCASE * 3 * grids_[0].n, st_);
     return check_hip("get_displacement");
   }
 
@@ -379,16 +418,17 @@ class Solver final : public SolverIface {
 
   Status loads(void* f) override {
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
-    forcing<T>(grids_[0], tpl_, s_, (T*)f, nullptr, Partials{}, nullptr, st_);
+    forcing<T>(grids_[0], tpl64_, s64_, (T*)f, Partials{}, nullptr, st_);
     return check_hip("load_vectors");
   }
 
   Status vcycle(const void* r, void* z) override {
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
     scal_set_all_active(aux_, st_);
-    vec_jacobi0<T>(grids_[0], (const T*)r, dinv0_, z_, aux_, st_);
     int nb = 0;
-    HMG_TRY(vcycle_rest((const T*)r, z_, (T*)z, aux_, &nb));
+    vec_mean_partial<T>(grids_[0], (const T*)r, part_, &nb, st_);
+    fin_mean(part_, nb, grids_[0].n, aux_, st_);
+    HMG_TRY(vcycle_apply((const T*)r, (T*)z, aux_, &nb));
     return check_hip("vcycle");
   }
 
@@ -409,12 +449,48 @@ class Solver final : public SolverIface {
     T* r = nullptr;
     T* z = nullptr;
     T* t = nullptr;
+    double* ms = nullptr;  // FP64 per-component means of r at this level (slots S_MEAN*)
   };
 
   static ModeK<T> cast_mode(const ModeK<double>& m) {
     return ModeK<T>{(T)m.ab, (T)m.b, (T)m.cs, (T)m.p, (T)m.q, (T)m.fg, (T)m.g, (T)m.z};
   }
-  double omega() const { return cfg_.omega > 0.0 ? cfg_.omega : 0.6; }
+  // Damping of block Jacobi on a level whose spectrum bound is lam: 1.6/lam
+  // (near the smoothing optimum 2/(lam + lam/4)); a configured omega is used
+  // when given but capped at 1.9/lam so the smoother stays convergent.
+  double omega_for(double lam) const {
+    return cfg_.omega > 0.0 ? std::min(cfg_.omega, 1.9 / lam) : 1.6 / lam;
+  }
+
+  // Largest eigenvalue of D^-1 K_l by power iteration (six start vectors; the
+  // largest Rayleigh estimate, increased by 5 % because power iteration
+  // approaches it from below).  Expects lev_[l].dinv to hold D^-1 (omega 1).
+  Status estimate_lambda(int l, double* out) {
+    Lev& lv = lev_[l];
+    const Grid& g = grids_[l];
+    const int64_t F = (int64_t)NCASE * 3 * g.n;
+    vec_pattern<T>(lv.z, F, st_);
+    for (int k = 0; k < 15; ++k) {
+      kc_apply<T>(g, lv.st, lv.z, lv.t, st_);                        // y = K x
+      vec_jacobi0<T>(g, lv.t, lv.dinv, lv.z, nullptr, nullptr, st_);  // x = D^-1 y
+    }
+    kc_apply<T>(g, lv.st, lv.z, lv.r, st_);
+    scal_set_all_active(aux_, st_);
+    int nb = 0;
+    vec_dot_cases<T>(g, lv.z, lv.r, aux_, part_, S_PQ, &nb, st_);   // x^T K x
+    fin_sum(part_, S_PQ, nb, aux_, true, st_);
+    vec_dot_cases<T>(g, lv.z, lv.t, aux_, part_, S_RZ, &nb, st_);   // x^T D x
+    fin_sum(part_, S_RZ, nb, aux_, true, st_);
+    HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+    const double* ha = hscal_ + S_NSLOT * 8;
+    double lam = 0.0;
+    for (int c = 0; c < NCASE; ++c)
+      if (ha[S_RZ * 8 + c] > 0.0) lam = std::max(lam, ha[S_PQ * 8 + c] / ha[S_RZ * 8 + c]);
+    if (!(lam > 0.0) || !std::isfinite(lam))
+      return fail(HMG_E_DEVICE, "spectral estimate failed on level %d", l);
+    *out = 1.05 * lam;
+    return Status{};
+  }
   static bool any(const bool* a) {
     for (int c = 0; c < NCASE; ++c)
       if (a[c]) return true;
@@ -427,17 +503,28 @@ class Solver final : public SolverIface {
     return check_hip("scalar readback");
   }
 
-  void set_mask(double* scal, const bool* on) {
-    double* h = hscal_ + 2 * S_NSLOT * 8 - 8;  // last 8 doubles of the pinned buffer
+  // Writes a per-case 0/1 mask into one slot of a device scalar array.
+  void set_slot(double* scal, int slot, const bool* on) {
+    double* h = hstage_;
     for (int c = 0; c < 8; ++c) h[c] = (c < NCASE && on[c]) ? 1.0 : 0.0;
-    (void)hipMemcpyAsync(scal + S_ACTIVE * 8, h, sizeof(double) * 8, hipMemcpyHostToDevice, st_);
+    (void)hipMemcpyAsync(scal + slot * 8, h, sizeof(double) * 8, hipMemcpyHostToDevice, st_);
     (void)hipStreamSynchronize(st_);
   }
+  void set_mask(double* scal, const bool* on) { set_slot(scal, S_ACTIVE, on); }
 
-  // Given level-0 r and its pre-smoothed correction z0 = omega D^-1 r, finish
-  // the V-cycle (Alg. 1, with the symmetric post-smoothing) into zout and
-  // leave per-block partials of r . zout in slot S_RZNEW.
-  Status vcycle_rest(const T* r0, const T* z0, T* zout, const double* scal, int* nb) {
+  // Means of r per case and component (FP64) into slots S_MEAN* of scal.
+  void residual_mean(double* scal) {
+    int nb = 0;
+    vec_mean_partial<T>(grids_[0], r_, part_, &nb, st_);
+    fin_mean(part_, nb, grids_[0].n, scal, st_);
+  }
+
+  // zout = M r0: one symmetric V(1,1) cycle (Alg. 1) started from zero, with
+  // the translation component of every residual removed in FP64 before the
+  // block-Jacobi smoother and the coarsest solve.  scal supplies the active
+  // cases and the means of r0; per-block partials of (r0 - m).zout are left in
+  // slot S_RZNEW.  Work buffers: q_ (pre-smoothed z0) and t_.
+  Status vcycle_apply(const T* r0, T* zout, const double* scal, int* nb) {
     const int L = levels();
     const Grid& g0 = grids_[0];
     if (L == 1) {
@@ -446,10 +533,10 @@ class Solver final : public SolverIface {
       return check_hip("vcycle");
     }
     Op0Launch<T> L0{g0, mk_, s_, st_};
-    op0_residual<T>(L0, z0, r0, t_, scal);
+    op0_residual<T>(L0, r0, dinv0_, q_, t_, scal);
     restrict_to<T>(g0, grids_[1], t_, lev_[1].r, scal, st_);
     descend(1, scal);
-    op0_post_smooth<T>(L0, z0, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
+    op0_post_smooth<T>(L0, q_, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
     return check_hip("vcycle");
   }
 
@@ -461,12 +548,15 @@ class Solver final : public SolverIface {
       coarse_solve<T>(g, Ainv_, lv.r, lv.z, scal, st_);
       return;
     }
-    vec_jacobi0<T>(g, lv.r, lv.dinv, lv.z, scal, st_);
-    kc_residual<T>(g, lv.st, lv.z, lv.r, lv.t, scal, st_);
+    int nb = 0;
+    vec_mean_partial<T>(g, lv.r, part_, &nb, st_);
+    fin_mean(part_, nb, g.n, lv.ms, st_);
+    vec_jacobi0<T>(g, lv.r, lv.dinv, lv.z, scal, lv.ms, st_);
+    kc_residual<T>(g, lv.st, lv.z, lv.r, lv.t, scal, lv.ms, st_);
     restrict_to<T>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
     descend(l + 1, scal);
     prolong_add<T>(g, grids_[l + 1], lv.z, lev_[l + 1].z, scal, false, st_);
-    kc_smooth<T>(g, lv.st, lv.z, lv.r, lv.dinv, lv.t, scal, st_);
+    kc_smooth<T>(g, lv.st, lv.z, lv.r, lv.dinv, lv.t, scal, lv.ms, st_);
     std::swap(lv.z, lv.t);
   }
 
@@ -476,10 +566,15 @@ class Solver final : public SolverIface {
   std::vector<Grid> grids_;
   DeviceArena arena_;
   ModeK<T> mk_{};
+  ModeK<double> mk64_{};
   LoadTpl<T> tpl_{};
-  LoadTpl<T> chh_{};
+  LoadTpl<double> tpl64_{};
+  LoadTpl<double> chh64_{};
   T *s_ = nullptr, *rho_ = nullptr, *dinv0_ = nullptr;
-  T *x_ = nullptr, *r_ = nullptr, *z_ = nullptr, *t_ = nullptr;
+  double* s64_ = nullptr;    // FP64 copies used by the residual recomputation and C^H
+  double* rho64_ = nullptr;
+  double* x_ = nullptr;      // iterate kept in FP64
+  T *r_ = nullptr, *z_ = nullptr, *t_ = nullptr;
   T *pa_ = nullptr, *pb_ = nullptr, *q_ = nullptr;
   T* st0_ = nullptr;
   std::vector<Lev> lev_;
@@ -490,8 +585,12 @@ class Solver final : public SolverIface {
   double *scal_ = nullptr, *aux_ = nullptr, *misc_ = nullptr;
   double *K0dev_ = nullptr, *msig_ = nullptr;
   int* bad_ = nullptr;
-  double* hscal_ = nullptr;
+  double* hscal_ = nullptr;  // pinned: device scalars read back (main, aux)
+  double* hstage_ = nullptr; // pinned: staging for host-to-device masks
   double mean_s_ = 1.0;
+  std::vector<double> omega_;   // block-Jacobi damping per level
+  std::vector<double> lambda_;  // spectral bound of D^-1 K per level
+  double last_true_[NCASE] = {};  // last recomputed residual norm per case
   bool have_density_ = false;
   bool have_solution_ = false;
 };
@@ -714,6 +813,14 @@ hmg_status hmg_level_dims(hmg_ctx ctx, int32_t level, int32_t dims_out[3]) {
   dims_out[0] = g.nx;
   dims_out[1] = g.ny;
   dims_out[2] = g.nz;
+  return HMG_OK;
+}
+
+hmg_status hmg_level_omega(hmg_ctx ctx, int32_t level, double* omega_out) {
+  if (!ctx || !omega_out) return HMG_E_INVALID;
+  if (level < 0 || level >= ctx->solver->levels())
+    return report(ctx, fail(HMG_E_INVALID, "level %d out of range", level));
+  *omega_out = ctx->solver->level_omega(level);
   return HMG_OK;
 }
 

@@ -31,57 +31,77 @@ __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
 
-// x += alpha p; r -= alpha q; z0 = Dinv r; partial ||r||^2.
+// Sums NV per-thread values over the block in a fixed order; out[j] valid in
+// thread 0 only.
+template <int NV>
+__device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* [VB/64][NV] */) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) lds[w * NV + j] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < VB / 64; ++i) s += lds[i * NV + j];
+      v[j] = s;
+    }
+}
+
+// x (FP64) += alpha p; r -= alpha q; partials of ||r||^2 and of sum(r) per
+// case and component (the translation component removed before smoothing).
 template <typename T>
-__global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ x, T* __restrict__ r,
-                                                    T* __restrict__ z0, const T* __restrict__ p,
-                                                    const T* __restrict__ q,
-                                                    const T* __restrict__ dinv, const double* scal,
+__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
+                                                    T* __restrict__ r, const T* __restrict__ p,
+                                                    const T* __restrict__ q, const double* scal,
                                                     Partials part) {
-  __shared__ double red[VB / 64];
+  __shared__ double red[(VB / 64) * NCASE * 4];
   bool on[NCASE];
-  T al[NCASE];
+  double al[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) {
     on[c] = case_on(scal, c);
-    al[c] = (T)scal[S_ALPHA * 8 + c];
+    al[c] = scal[S_ALPHA * 8 + c];
   }
-  double acc[NCASE];
+  double acc[NCASE * 4];  // [c]: ||r||^2, [6 + 3c + k]: sum r
 #pragma unroll
-  for (int c = 0; c < NCASE; ++c) acc[c] = 0.0;
+  for (int j = 0; j < NCASE * 4; ++j) acc[j] = 0.0;
   const int64_t n = g.n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
-    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
-      T rv[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t o = (int64_t)(c * 3 + k) * n + i;
-        x[o] = x[o] + al[c] * p[o];
-        rv[k] = r[o] - al[c] * q[o];
-        r[o] = rv[k];
-        acc[c] += (double)rv[k] * (double)rv[k];
+        x[o] = x[o] + al[c] * (double)p[o];
+        const T rv = r[o] - (T)al[c] * q[o];
+        r[o] = rv;
+        acc[c] += (double)rv * (double)rv;
+        acc[NCASE + 3 * c + k] += (double)rv;
       }
-      z0[(int64_t)(c * 3 + 0) * n + i] = dxx * rv[0] + dxy * rv[1] + dxz * rv[2];
-      z0[(int64_t)(c * 3 + 1) * n + i] = dxy * rv[0] + dyy * rv[1] + dyz * rv[2];
-      z0[(int64_t)(c * 3 + 2) * n + i] = dxz * rv[0] + dyz * rv[1] + dzz * rv[2];
     }
   }
+  block_sum_multi<NCASE * 4>(acc, red);
+  if (threadIdx.x == 0)
 #pragma unroll
-  for (int c = 0; c < NCASE; ++c) {
-    const double t = block_sum<VB / 64>(acc[c], red);
-    if (threadIdx.x == 0) part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = t;
-  }
+    for (int c = 0; c < NCASE; ++c) {
+      part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = acc[c];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = acc[NCASE + 3 * c + k];
+    }
 }
 
+// z = Dinv (r - m), m the per-component mean in `mean` (slots S_MEAN*, may be NULL).
 template <typename T>
 __global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const T* __restrict__ r,
                                                      const T* __restrict__ dinv, T* __restrict__ z,
-                                                     const double* scal) {
+                                                     const double* scal, const double* mean) {
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
@@ -93,8 +113,15 @@ __global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const T* __restrict
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
-      const T r0 = r[(int64_t)(c * 3 + 0) * n + i], r1 = r[(int64_t)(c * 3 + 1) * n + i];
-      const T r2 = r[(int64_t)(c * 3 + 2) * n + i];
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+      if (mean) {
+        m0 = mean[S_MEAN0 * 8 + c];
+        m1 = mean[S_MEAN1 * 8 + c];
+        m2 = mean[S_MEAN2 * 8 + c];
+      }
+      const T r0 = (T)((double)r[(int64_t)(c * 3 + 0) * n + i] - m0);
+      const T r1 = (T)((double)r[(int64_t)(c * 3 + 1) * n + i] - m1);
+      const T r2 = (T)((double)r[(int64_t)(c * 3 + 2) * n + i] - m2);
       z[(int64_t)(c * 3 + 0) * n + i] = dxx * r0 + dxy * r1 + dxz * r2;
       z[(int64_t)(c * 3 + 1) * n + i] = dxy * r0 + dyy * r1 + dyz * r2;
       z[(int64_t)(c * 3 + 2) * n + i] = dxz * r0 + dyz * r1 + dzz * r2;
@@ -107,6 +134,25 @@ __global__ void fill_kernel(T* __restrict__ a, int64_t count, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
+}
+
+template <typename T>
+__global__ void pattern_kernel(T* __restrict__ a, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    a[i] = (T)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+  }
+}
+
+template <typename S, typename D>
+__global__ void convert_kernel(D* __restrict__ d, const S* __restrict__ s, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (D)s[i];
 }
 
 template <typename T>
@@ -215,8 +261,10 @@ __global__ void fin_beta_kernel(double* scal) {
   if (c >= NCASE) return;
   if (scal[S_ACTIVE * 8 + c] == 0.0) return;
   const double rz = scal[S_RZ * 8 + c], rzn = scal[S_RZNEW * 8 + c];
-  scal[S_BETA * 8 + c] = rz != 0.0 ? rzn / rz : 0.0;
+  const bool restart = scal[S_RESTART * 8 + c] != 0.0;
+  scal[S_BETA * 8 + c] = (rz != 0.0 && !restart) ? rzn / rz : 0.0;
   scal[S_RZ * 8 + c] = rzn;
+  scal[S_RESTART * 8 + c] = 0.0;
 }
 
 __global__ void fin_mean_kernel(Partials part, int nblk, int64_t n, double* scal) {
@@ -235,6 +283,7 @@ __global__ void all_active_kernel(double* scal) {
     scal[S_ACTIVE * 8 + c] = 1.0;
     scal[S_BETA * 8 + c] = 0.0;
     scal[S_ALPHA * 8 + c] = 0.0;
+    scal[S_RESTART * 8 + c] = 0.0;
   }
 }
 
@@ -267,23 +316,35 @@ inline int blocks_for(int64_t n) {
 
 int vec_blocks(const Grid& g) { return blocks_for(g.n); }
 
+template <typename S, typename D>
+void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL((convert_kernel<S, D>), dim3(blocks_for(count)), dim3(VB), 0, st, dst, src,
+                     count);
+}
+template void vec_convert<float, double>(double*, const float*, int64_t, hipStream_t);
+template void vec_convert<double, float>(float*, const double*, int64_t, hipStream_t);
+template void vec_convert<double, double>(double*, const double*, int64_t, hipStream_t);
+
 template <typename T>
-void vec_update_xrz(const Grid& g, T* x, T* r, T* z0, const T* p, const T* q, const T* dinv,
-                    const double* scal, Partials part, int* nblk_out, hipStream_t st) {
+void vec_update_xr(const Grid& g, double* x, T* r, const T* p, const T* q, const double* scal,
+                   Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, x, r, z0, p, q, dinv, scal,
-                     part);
+  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, x, r, p, q, scal, part);
   *nblk_out = nb;
 }
 template <typename T>
 void vec_jacobi0(const Grid& g, const T* r, const T* dinv, T* z, const double* scal,
-                 hipStream_t st) {
+                 const double* mean, hipStream_t st) {
   hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, r, dinv, z,
-                     scal);
+                     scal, mean);
 }
 template <typename T>
 void vec_fill(T* a, int64_t count, T v, hipStream_t st) {
   hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count, v);
+}
+template <typename T>
+void vec_pattern(T* a, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(pattern_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count);
 }
 template <typename T>
 void vec_copy(T* d, const T* s, int64_t count, hipStream_t st) {
@@ -336,10 +397,12 @@ void scal_set_all_active(double* scal, hipStream_t st) {
 }
 
 #define HMG_INST(T)                                                                             \
-  template void vec_update_xrz<T>(const Grid&, T*, T*, T*, const T*, const T*, const T*,        \
-                                  const double*, Partials, int*, hipStream_t);                  \
-  template void vec_jacobi0<T>(const Grid&, const T*, const T*, T*, const double*, hipStream_t); \
+  template void vec_update_xr<T>(const Grid&, double*, T*, const T*, const T*, const double*,   \
+                                 Partials, int*, hipStream_t);                                  \
+  template void vec_jacobi0<T>(const Grid&, const T*, const T*, T*, const double*,              \
+                               const double*, hipStream_t);                                     \
   template void vec_fill<T>(T*, int64_t, T, hipStream_t);                                       \
+  template void vec_pattern<T>(T*, int64_t, hipStream_t);                                       \
   template void vec_copy<T>(T*, const T*, int64_t, hipStream_t);                                \
   template void vec_dot_cases<T>(const Grid&, const T*, const T*, const double*, Partials, int,  \
                                  int*, hipStream_t);                                            \

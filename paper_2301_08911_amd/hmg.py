@@ -148,6 +148,11 @@ class Context:
         self._check(self.lib.hmg_level_dims(self._h, level, d))
         return tuple(d[:])
 
+    def level_omega(self, level: int) -> float:
+        v = ctypes.c_double()
+        self._check(self.lib.hmg_level_omega(self._h, level, ctypes.byref(v)))
+        return v.value
+
     def apply_operator(self, level: int, u: torch.Tensor, y: torch.Tensor | None = None):
         n = int(np.prod(self.level_dims(level)))
         y = self.new_field(level) if y is None else y
