@@ -155,6 +155,28 @@ hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev);
 /* Message of the last failed call on this context ("" if none). */
 const char* hmg_last_error(hmg_ctx ctx);
 
+/* ---- kernel timing --------------------------------------------------------- */
+
+/* Kernels whose launches inside hmg_solve_cases can be timed. */
+typedef enum {
+  HMG_K_MATVEC = 0,        /* p = z + beta p, q = K p, p.q          (level-0 operator) */
+  HMG_K_RESIDUAL = 1,      /* z0 = D^-1 (r - m), t = (r - m) - K z0  (level-0 operator) */
+  HMG_K_POST_SMOOTH = 2,   /* z = z1 + D^-1 ((r - m) - K z1), z1 = z0 + P e            */
+  HMG_K_UPDATE = 3,        /* x += alpha p (FP64), r -= alpha q                          */
+  HMG_K_TRUE_RESIDUAL = 4  /* r = f - K x in FP64                                        */
+} hmg_kernel;
+
+/* enable != 0 clears the counters and starts recording a HIP event pair around
+ * every launch of the kernels above (on the context stream); 0 stops. */
+hmg_status hmg_profile(hmg_ctx ctx, int32_t enable);
+
+/* Launch count, summed event time (ms) and summed algorithmic bytes of one
+ * kernel since profiling was enabled.  Algorithmic bytes are the unique bytes
+ * the launch must move for its active cases (inputs read once, outputs written
+ * once; halo re-reads not counted).  Synchronizes the stream. */
+hmg_status hmg_profile_read(hmg_ctx ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                            double* total_bytes);
+
 /* ---- inspection entry points (used by the parity tests) ------------------ */
 
 /* Number of multigrid levels and the cells per axis of one level. */

@@ -10,7 +10,7 @@ SYMBOLS = (
     "hmg_create", "hmg_destroy", "hmg_set_density", "hmg_solve_cases", "hmg_elastic_tensor",
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
     "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
-    "hmg_load_vectors", "hmg_vcycle", "hmg_transfer",
+    "hmg_load_vectors", "hmg_vcycle", "hmg_transfer", "hmg_profile", "hmg_profile_read",
 )
 
 
@@ -59,6 +59,8 @@ def load() -> ctypes.CDLL:
         "hmg_load_vectors": ([vp, vp], i32),
         "hmg_vcycle": ([vp, vp, vp], i32),
         "hmg_transfer": ([vp, i32, i32, vp, vp], i32),
+        "hmg_profile": ([vp, i32], i32),
+        "hmg_profile_read": ([vp, i32, P(ctypes.c_int64), P(f64), P(f64)], i32),
     }
     for name, (args, ret) in sig.items():
         fn = getattr(lib, name)

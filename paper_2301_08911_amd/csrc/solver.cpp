@@ -52,6 +52,85 @@ class DeviceArena {
   std::vector<void*> ptrs_;
 };
 
+// Optional per-kernel timing with HIP events recorded on the context stream
+// around the tracked launches; elapsed times are harvested when read.
+class KernelClock {
+ public:
+  static constexpr int NK = 5;
+  ~KernelClock() {
+    for (auto& p : pending_) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+  }
+  void enable(bool on) {
+    on_ = on;
+    if (on) {
+      harvest();
+      for (int k = 0; k < NK; ++k) {
+        ms_[k] = 0.0;
+        bytes_[k] = 0.0;
+        count_[k] = 0;
+      }
+    }
+  }
+  template <class F>
+  void timed(int k, double bytes, hipStream_t st, F&& launch) {
+    if (!on_) {
+      launch();
+      return;
+    }
+    Rec r{k, bytes, get(), get()};
+    (void)hipEventRecord(r.a, st);
+    launch();
+    (void)hipEventRecord(r.b, st);
+    pending_.push_back(r);
+    if (pending_.size() > 4096) harvest();
+  }
+  void read(int k, int64_t* count, double* ms, double* bytes) {
+    harvest();
+    *count = count_[k];
+    *ms = ms_[k];
+    *bytes = bytes_[k];
+  }
+
+ private:
+  struct Rec {
+    int k;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  hipEvent_t get() {
+    if (!pool_.empty()) {
+      hipEvent_t e = pool_.back();
+      pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void harvest() {
+    for (auto& p : pending_) {
+      (void)hipEventSynchronize(p.b);
+      float t = 0.0f;
+      (void)hipEventElapsedTime(&t, p.a, p.b);
+      ms_[p.k] += t;
+      bytes_[p.k] += p.bytes;
+      count_[p.k] += 1;
+      pool_.push_back(p.a);
+      pool_.push_back(p.b);
+    }
+    pending_.clear();
+  }
+  bool on_ = false;
+  std::vector<Rec> pending_;
+  std::vector<hipEvent_t> pool_;
+  double ms_[NK] = {}, bytes_[NK] = {};
+  int64_t count_[NK] = {};
+};
+
 // Precision-independent interface of a typed solver.
 class SolverIface {
  public:
@@ -71,6 +150,7 @@ class SolverIface {
   virtual int levels() const = 0;
   virtual Grid level_grid(int l) const = 0;
   virtual double level_omega(int l) const = 0;
+  KernelClock clock;
 };
 
 Status fail(hmg_status code, const char* fmt, ...) {
@@ -281,6 +361,7 @@ class Solver final : public SolverIface {
     }
     T* pold = pa_;
     T* pnew = pb_;
+    active_count_ = count(active);
     if (any(active)) {
       HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
@@ -290,10 +371,15 @@ class Solver final : public SolverIface {
     int it = 0;
     while (any(active) && it < max_iter) {
       ++it;
-      op0_matvec_p<T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
+      const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T);
+      clock.timed(HMG_K_MATVEC, vn * (nact * 12 * TB + TB), st_, [&] {
+        op0_matvec_p<T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
+      });
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      vec_update_xr<T>(g0, x_, r_, pnew, q_, scal_, part_, &nb, st_);
+      clock.timed(HMG_K_UPDATE, vn * nact * (48 + 12 * TB), st_, [&] {
+        vec_update_xr<T>(g0, x_, r_, pnew, q_, scal_, part_, &nb, st_);
+      });
       fin_sum(part_, S_RR, nb, scal_, false, st_);
       fin_mean(part_, nb, g0.n, scal_, st_);
       std::swap(pold, pnew);
@@ -315,7 +401,8 @@ class Solver final : public SolverIface {
         // Confirm on the residual f - K x recomputed in FP64 before a case
         // stops; the recomputed residual also replaces the recursive one.
         set_mask(aux_, check);
-        op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb);
+        clock.timed(HMG_K_TRUE_RESIDUAL, (double)g0.n * (count(check) * (24 + 3 * sizeof(T)) + 8),
+                    st_, [&] { op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb); });
         fin_sum(part_, S_TRUE, nb, aux_, false, st_);
         HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
         const double* ha = hscal_ + S_NSLOT * 8;
@@ -338,6 +425,7 @@ class Solver final : public SolverIface {
         residual_mean(scal_);
       }
       if (!any(active)) break;
+      active_count_ = count(active);
       HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
       fin_beta(scal_, st_);
@@ -425,6 +513,7 @@ class Solver final : public SolverIface {
   Status vcycle(const void* r, void* z) override {
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
     scal_set_all_active(aux_, st_);
+    active_count_ = NCASE;
     int nb = 0;
     vec_mean_partial<T>(grids_[0], (const T*)r, part_, &nb, st_);
     fin_mean(part_, nb, grids_[0].n, aux_, st_);
@@ -491,6 +580,11 @@ class Solver final : public SolverIface {
     *out = 1.05 * lam;
     return Status{};
   }
+  static int count(const bool* a) {
+    int k = 0;
+    for (int c = 0; c < NCASE; ++c) k += a[c] ? 1 : 0;
+    return k;
+  }
   static bool any(const bool* a) {
     for (int c = 0; c < NCASE; ++c)
       if (a[c]) return true;
@@ -533,10 +627,14 @@ class Solver final : public SolverIface {
       return check_hip("vcycle");
     }
     Op0Launch<T> L0{g0, mk_, s_, st_};
-    op0_residual<T>(L0, r0, dinv0_, q_, t_, scal);
+    const double vn = (double)g0.n, TB = sizeof(T), nact = active_count_;
+    clock.timed(HMG_K_RESIDUAL, vn * (nact * 9 * TB + 7 * TB), st_,
+                [&] { op0_residual<T>(L0, r0, dinv0_, q_, t_, scal); });
     restrict_to<T>(g0, grids_[1], t_, lev_[1].r, scal, st_);
     descend(1, scal);
-    op0_post_smooth<T>(L0, q_, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
+    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 9.375 * TB + 7 * TB), st_, [&] {
+      op0_post_smooth<T>(L0, q_, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
+    });
     return check_hip("vcycle");
   }
 
@@ -588,6 +686,7 @@ class Solver final : public SolverIface {
   double* hscal_ = nullptr;  // pinned: device scalars read back (main, aux)
   double* hstage_ = nullptr; // pinned: staging for host-to-device masks
   double mean_s_ = 1.0;
+  int active_count_ = NCASE;
   std::vector<double> omega_;   // block-Jacobi damping per level
   std::vector<double> lambda_;  // spectral bound of D^-1 K per level
   double last_true_[NCASE] = {};  // last recomputed residual norm per case
@@ -813,6 +912,22 @@ hmg_status hmg_level_dims(hmg_ctx ctx, int32_t level, int32_t dims_out[3]) {
   dims_out[0] = g.nx;
   dims_out[1] = g.ny;
   dims_out[2] = g.nz;
+  return HMG_OK;
+}
+
+hmg_status hmg_profile(hmg_ctx ctx, int32_t enable) {
+  if (!ctx) return HMG_E_INVALID;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->solver->clock.enable(enable != 0);
+  return HMG_OK;
+}
+
+hmg_status hmg_profile_read(hmg_ctx ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                            double* total_bytes) {
+  if (!ctx || !launches || !total_ms || !total_bytes) return HMG_E_INVALID;
+  if (kernel < 0 || kernel >= KernelClock::NK)
+    return report(ctx, fail(HMG_E_INVALID, "unknown kernel id %d", kernel));
+  ctx->solver->clock.read(kernel, launches, total_ms, total_bytes);
   return HMG_OK;
 }
 

@@ -15,6 +15,7 @@ import torch
 from . import _lib
 
 OK, E_INVALID, E_OOM, E_DEVICE, E_NOT_CONVERGED, E_STATE = range(6)
+KERNELS = {"matvec": 0, "residual": 1, "post_smooth": 2, "update": 3, "true_residual": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "mixed_bf16": 2, "mixed_fp16": 3}
 
 
@@ -147,6 +148,19 @@ class Context:
         d = (ctypes.c_int32 * 3)()
         self._check(self.lib.hmg_level_dims(self._h, level, d))
         return tuple(d[:])
+
+    def profile(self, enable: bool):
+        self._check(self.lib.hmg_profile(self._h, int(enable)))
+
+    def profile_read(self) -> dict:
+        """{kernel: (launches, total_ms, total_algorithmic_bytes)} since profile(True)."""
+        out = {}
+        for name, k in KERNELS.items():
+            cnt, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            self._check(self.lib.hmg_profile_read(self._h, k, ctypes.byref(cnt), ctypes.byref(ms),
+                                                  ctypes.byref(by)))
+            out[name] = (cnt.value, ms.value, by.value)
+        return out
 
     def level_omega(self, level: int) -> float:
         v = ctypes.c_double()

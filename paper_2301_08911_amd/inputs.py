@@ -17,8 +17,16 @@ numpy arrays of shape ``(nz, ny, nx)`` (C order, so ``.ravel()`` gives idx).
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+
+try:  # multi-threaded pocketfft; same transform as numpy.fft
+    import scipy.fft as _fft
+    _FFT_KW = {"workers": min(16, os.cpu_count() or 1)}
+except ImportError:  # pragma: no cover
+    _fft = np.fft
+    _FFT_KW = {}
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -83,7 +91,10 @@ def smoothed_noise(shape, seed: int, sigma: float = 3.0) -> np.ndarray:
         ker = np.fft.rfft(_periodic_gauss_1d(length, sigma))
         shp = [1, 1, 1]
         shp[axis] = ker.shape[0]
-        v = np.fft.irfft(np.fft.rfft(v, axis=axis) * ker.reshape(shp), n=length, axis=axis)
+        spec = _fft.rfft(v, axis=axis, **_FFT_KW)
+        spec *= ker.reshape(shp)
+        v = _fft.irfft(spec, n=length, axis=axis, **_FFT_KW)
+        del spec
     return v
 
 
