@@ -70,6 +70,7 @@ enum Slot {
   S_MEAN2,
   S_TRUE,       // recomputed ||f - K x||^2
   S_RESTART,    // 1: the residual was just recomputed; restart the direction (beta = 0)
+  S_XALPHA,     // step not yet applied to x: x += S_XALPHA * p (done by the next matvec)
   S_NSLOT
 };
 
@@ -89,17 +90,19 @@ template <typename T> struct Op0Launch {
 
 template <typename T>
 void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal);
+// p_new = z + beta p_old, q = K p_new, partial p.q; also x += alpha_x p_old
+// (the pending iterate update) at owned vertices.
 template <typename T>
-void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q,
+void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q, double* x,
                   const double* scal, Partials part, int* nblk_out);
 // z0 = Dinv (r - m) (also written out) and t = (r - m) - K z0; m from scal S_MEAN*.
 template <typename T>
 void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
                   const double* scal);
-// z1 = z0 + P ec; zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW.
+// zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW.
 template <typename T>
-void op0_post_smooth(const Op0Launch<T>& L, const T* z0, const T* ec, Grid gc, const T* r,
-                     const T* dinv, T* zout, const double* scal, Partials part, int* nblk_out);
+void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
+                     const double* scal, Partials part, int* nblk_out);
 // r = f - K x evaluated in FP64 (x, s and the constants in double), stored as R.
 template <typename R>
 void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
@@ -121,10 +124,13 @@ template <typename T>
 void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipStream_t stm);
 
 // ---------------------------------------------------------------- vectors
-// x (FP64) += alpha p; r -= alpha q; partials ||r||^2 (S_RR) and sum r (S_MEAN*).
+// r -= alpha q; partials ||r||^2 (S_RR) and sum r (S_MEAN*).  The iterate
+// update is deferred (slot S_XALPHA); vec_flush_x applies it: x += alpha_x p.
 template <typename T>
-void vec_update_xr(const Grid& g, double* x, T* r, const T* p, const T* q, const double* scal,
-                   Partials part, int* nblk_out, hipStream_t st);
+void vec_update_r(const Grid& g, T* r, const T* q, const double* scal, Partials part,
+                  int* nblk_out, hipStream_t st);
+template <typename T>
+void vec_flush_x(const Grid& g, double* x, const T* p, double* scal, hipStream_t st);
 template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);
 // z = Dinv (r - m) with m from `mean` slots S_MEAN* (NULL: no shift).

@@ -22,8 +22,8 @@ constexpr int TYE = 8;   // element rows along y per tile (wavefronts per block)
 constexpr int OX = TXE - 1, OY = TYE - 1;  // owned vertex columns per tile
 constexpr int PX = TXE + 1, PY = TYE + 1;  // staged vertex plane
 constexpr int NTHR = TXE * TYE;
-constexpr int NLOAD = 3 * PY * PX;
-constexpr int NSLOT = (NLOAD + NTHR - 1) / NTHR;
+constexpr int NVTX = PY * PX;                       // vertices of a staged plane
+constexpr int NSLOT = (NVTX + NTHR - 1) / NTHR;     // plane vertices per thread
 
 struct TileGeom {
   int ntx, nty, nzc, lz, ntiles;
@@ -92,6 +92,13 @@ __device__ __forceinline__ void mode_apply(const ModeK<T>& K, T s, const T (&uh)
   wh[0][0] = wh[0][1] = wh[0][2] = T(0);
 }
 
+// Workgroup barrier that waits only for this wave's LDS traffic, so global loads
+// issued for the next plane stay in flight across it (the plain barrier also
+// drains outstanding global memory operations).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
@@ -125,7 +132,7 @@ template <typename T, class Op>
 __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk,
                                                    const T* __restrict__ s) {
   __shared__ T plane[2][3][PY][PX];
-  __shared__ T contrib[4][3][TYE][TXE];
+  __shared__ T contrib[2][4][3][TYE][TXE];
   __shared__ double red[NTHR / 64];
 
   const int j = logical_block();
@@ -142,40 +149,55 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
   const int tid = threadIdx.x, lx = tid & (TXE - 1), ly = tid / TXE;
   const int64_t nxy = (int64_t)g.nx * g.ny;
 
-  // Plane-load slots of this thread (same for every plane).
+  // Plane-load slots of this thread (same vertices of every plane); each slot
+  // produces the three components of one vertex.
   int64_t ld_xy[NSLOT];
-  int ld_lds[NSLOT], ld_k[NSLOT], ld_gx[NSLOT], ld_gy[NSLOT];
+  int ld_pos[NSLOT], ld_gx[NSLOT], ld_gy[NSLOT];
   bool ld_own[NSLOT], ld_ok[NSLOT];
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl) {
     const int i = tid + sl * NTHR;
-    ld_ok[sl] = i < NLOAD;
+    ld_ok[sl] = i < NVTX;
     const int ii = ld_ok[sl] ? i : 0;
-    const int k = ii / (PY * PX);
-    const int rr = ii - k * (PY * PX);
-    const int py = rr / PX, px = rr - py * PX;
+    const int py = ii / PX, px = ii - py * PX;
     const int ux = x0 - 1 + px, uy = y0 - 1 + py;
     ld_gx[sl] = modp(ux, g.nx);
     ld_gy[sl] = modp(uy, g.ny);
     ld_xy[sl] = ld_gx[sl] + (int64_t)g.nx * ld_gy[sl];
-    ld_lds[sl] = (k * PY + py) * PX + px;
-    ld_k[sl] = k;
+    ld_pos[sl] = ii;
     ld_own[sl] = px >= 1 && px <= OX && py >= 1 && py <= OY && ux < g.nx && uy < g.ny;
   }
   const int ex = modp(x0 - 1 + lx, g.nx), ey = modp(y0 - 1 + ly, g.ny);
   const int64_t exy = ex + (int64_t)g.nx * ey;
   const bool outv = lx >= 1 && ly >= 1 && (x0 - 1 + lx) < g.nx && (y0 - 1 + ly) < g.ny;
 
-  auto load_plane = [&](int buf, int zu) {
+  // Global loads of one plane are issued a plane ahead into raw registers
+  // (fetch); the op's arithmetic and its owned-vertex side writes run when the
+  // plane is staged into LDS (stage), so the loads overlap a plane of compute.
+  typename Op::Raw raw[NSLOT];
+  int fetched_z = 0;
+  auto fetch_plane = [&](int zu) {
+    const int64_t zoff = nxy * modp(zu, g.nz);
+    const bool ownz = zu >= z0 && zu < z1;
+    fetched_z = zu;
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; ++sl)
+      if (ld_ok[sl]) op.fetch(c, zoff + ld_xy[sl], ld_own[sl] && ownz, raw[sl]);
+  };
+  auto stage_plane = [&](int buf) {
+    const int zu = fetched_z;
     const int gz = modp(zu, g.nz);
     const bool ownz = zu >= z0 && zu < z1;
     const int64_t zoff = nxy * gz;
     T* base = &plane[buf][0][0][0];
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl)
-      if (ld_ok[sl])
-        base[ld_lds[sl]] =
-            op.load(c, ld_k[sl], zoff + ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz);
+      if (ld_ok[sl]) {
+        T v[3];
+        op.finish(c, zoff + ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz, raw[sl], v);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) base[k * NVTX + ld_pos[sl]] = v[k];
+      }
   };
   auto plane_modes = [&](int buf, T (&tm)[4][3], T (&own)[3]) {
 #pragma unroll
@@ -187,67 +209,90 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
     }
   };
 
+  // One barrier per plane.  Iteration ez: (A) write the vertex-plane ez-1
+  // contributions computed in the previous iteration and stage vertex plane
+  // ez+1 (prefetched a plane earlier); barrier; (B) gather plane ez-1 and run
+  // its epilogue, then compute element plane ez.  LDS planes and contribution
+  // buffers alternate between iterations.
   double acc0 = 0.0, acc1 = 0.0;
-  T tp[4][3], ga[4][3], uown[3];
-  load_plane(0, z0 - 1);
-  __syncthreads();
-  plane_modes(0, tp, uown);
+  T tp[4][3], ga[4][3], yq[4][3], ucur[3], uprev[3];
+  fetch_plane(z0 - 1);
+  stage_plane(0);
+  fetch_plane(z0);
+  lds_barrier();
+  plane_modes(0, tp, ucur);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ga[q][k] = T(0);
-  int cur = 0;
-  for (int ez = z0 - 1; ez < z1; ++ez) {
-    const int nxt = cur ^ 1;
-    load_plane(nxt, ez + 1);
-    __syncthreads();
-    T tn[4][3], unext[3];
-    plane_modes(nxt, tn, unext);
-    const T se = s[nxy * modp(ez, g.nz) + exy];
-    T uh[8][3], wh[8][3];
+    for (int k = 0; k < 3; ++k) ga[q][k] = yq[q][k] = T(0);
+  uprev[0] = uprev[1] = uprev[2] = T(0);
+  bool have_y = false;
+  // Per-thread operands of the epilogue (own vertex) and the element scale are
+  // also loaded one plane ahead.
+  typename Op::ERaw eraw;
+  T s_next = s[nxy * modp(z0 - 1, g.nz) + exy];
+  for (int ez = z0 - 1; ez <= z1; ++ez) {
+    const int it = ez - z0 + 1;  // 0, 1, 2, ...
+    const int cb = it & 1;       // contribution buffer of this iteration
+    const int pb = (it + 1) & 1; // plane buffer receiving vertex plane ez + 1
+    if (have_y) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        uh[q][k] = tp[q][k] + tn[q][k];      // m2 = 0
-        uh[q + 4][k] = tp[q][k] - tn[q][k];  // m2 = 1
-      }
-    mode_apply(mk, se, uh, wh);
-    if (ez >= z0) {
-      T gq[4][3];
+        for (int k = 0; k < 3; ++k) contrib[cb][b][k][ly][lx] = yq[b][k];
+    }
+    if (ez < z1) {
+      stage_plane(pb);
+      if (ez + 2 <= z1) fetch_plane(ez + 2);
+    }
+    lds_barrier();
+    if (have_y && outv) {
+      T ku[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        ku[k] = (contrib[cb][0][k][ly][lx] + contrib[cb][1][k][ly][lx - 1]) +
+                (contrib[cb][2][k][ly - 1][lx] + contrib[cb][3][k][ly - 1][lx - 1]);
+      op.store(c, nxy * (ez - 1) + exy, ex, ey, ez - 1, ku, uprev, eraw, acc0, acc1);
+    }
+    // epilogue operands of vertex plane ez (used next iteration)
+    if (outv && ez >= z0 && ez < z1) op.efetch(c, nxy * ez + exy, eraw);
+    have_y = false;
+    if (ez < z1) {
+      T tn[4][3], unext[3];
+      plane_modes(pb, tn, unext);
+      const T se = s_next;
+      if (ez + 1 < z1) s_next = s[nxy * modp(ez + 1, g.nz) + exy];
+      T uh[8][3], wh[8][3];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gq[q][k] = ga[q][k] + (wh[q][k] + wh[q + 4][k]);
+        for (int k = 0; k < 3; ++k) {
+          uh[q][k] = tp[q][k] + tn[q][k];      // m2 = 0
+          uh[q + 4][k] = tp[q][k] - tn[q][k];  // m2 = 1
+        }
+      mode_apply(mk, se, uh, wh);
+      if (ez >= z0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T g0 = ga[0][k] + (wh[0][k] + wh[4][k]), g1 = ga[1][k] + (wh[1][k] + wh[5][k]);
+          const T g2 = ga[2][k] + (wh[2][k] + wh[6][k]), g3 = ga[3][k] + (wh[3][k] + wh[7][k]);
+          bfly4(g0, g1, g2, g3, yq[0][k], yq[1][k], yq[2][k], yq[3][k]);
+        }
+        have_y = true;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ga[q][k] = wh[q][k] - wh[q + 4][k];
+          tp[q][k] = tn[q][k];
+        }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        T y0v, y1v, y2v, y3v;
-        bfly4(gq[0][k], gq[1][k], gq[2][k], gq[3][k], y0v, y1v, y2v, y3v);
-        contrib[0][k][ly][lx] = y0v;
-        contrib[1][k][ly][lx] = y1v;
-        contrib[2][k][ly][lx] = y2v;
-        contrib[3][k][ly][lx] = y3v;
-      }
-      __syncthreads();
-      if (outv) {
-        T ku[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          ku[k] = (contrib[0][k][ly][lx] + contrib[1][k][ly][lx - 1]) +
-                  (contrib[2][k][ly - 1][lx] + contrib[3][k][ly - 1][lx - 1]);
-        op.store(c, nxy * ez + exy, ex, ey, ez, ku, uown, acc0, acc1);
+        uprev[k] = ucur[k];
+        ucur[k] = unext[k];
       }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ga[q][k] = wh[q][k] - wh[q + 4][k];
-        tp[q][k] = tn[q][k];
-      }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) uown[k] = unext[k];
-    cur = nxt;
   }
   if (Op::NACC > 0) {
     const double t0 = block_sum<NTHR / 64>(acc0, red);
@@ -275,17 +320,29 @@ struct OpApply {
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
-    return in[(int64_t)(c * 3 + k) * n + i];
+  struct Raw {
+    T u[3];
+  };
+  struct ERaw {};
+  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.u[k] = in[(int64_t)(c * 3 + k) * n + i];
   }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, double&,
-                        double&) const {
+  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = w.u[k];
+  }
+  __device__ void efetch(int, int64_t, ERaw&) const {}
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, const ERaw&,
+                        double&, double&) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = ku[k];
   }
 };
 
-// p_new = z + beta p_old (written at owned vertices), q = K p_new, acc p.q
+// p_new = z + beta p_old (written at owned vertices), q = K p_new, acc p.q.
+// The iterate update of the previous iteration, x += alpha_x p_old (FP64), is
+// applied at owned vertices on the way (alpha_x from slot S_XALPHA).
 template <typename T>
 struct OpMatvecP {
   static constexpr int NACC = 1;
@@ -293,20 +350,44 @@ struct OpMatvecP {
   const T* pold;
   T* pnew;
   T* q;
+  double* x;
   int64_t n;
   const double* scal;
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int, int, int, bool own) const {
-    const int64_t o = (int64_t)(c * 3 + k) * n + i;
-    const T beta = (T)scal[S_BETA * 8 + c];
-    const T v = z[o] + beta * pold[o];
-    if (own) pnew[o] = v;
-    return v;
+  struct Raw {
+    T z[3], p[3];
+    double x[3];
+  };
+  struct ERaw {};
+  __device__ void fetch(int c, int64_t i, bool own, Raw& w) const {
+    const bool upd = own && scal[S_XALPHA * 8 + c] != 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = (int64_t)(c * 3 + k) * n + i;
+      w.z[k] = z[o];
+      w.p[k] = pold[o];
+      w.x[k] = upd ? x[o] : 0.0;
+    }
   }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, double& a0,
-                        double&) const {
+  __device__ void finish(int c, int64_t i, int, int, int, bool own, const Raw& w,
+                         T (&v)[3]) const {
+    const T beta = (T)scal[S_BETA * 8 + c];
+    const double ax = scal[S_XALPHA * 8 + c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = (int64_t)(c * 3 + k) * n + i;
+      v[k] = w.z[k] + beta * w.p[k];
+      if (own) {
+        pnew[o] = v[k];
+        if (ax != 0.0) x[o] = w.x[k] + ax * (double)w.p[k];
+      }
+    }
+  }
+  __device__ void efetch(int, int64_t, ERaw&) const {}
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, const ERaw&,
+                        double& a0, double&) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       q[(int64_t)(c * 3 + k) * n + i] = ku[k];
@@ -331,82 +412,89 @@ struct OpResidual {
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int, int, int, bool own) const {
-    const double r0 = (double)r[(int64_t)(c * 3 + 0) * n + i] - scal[S_MEAN0 * 8 + c];
-    const double r1 = (double)r[(int64_t)(c * 3 + 1) * n + i] - scal[S_MEAN1 * 8 + c];
-    const double r2 = (double)r[(int64_t)(c * 3 + 2) * n + i] - scal[S_MEAN2 * 8 + c];
-    // dinv planes: xx, yy, zz, xy, yz, xz
-    const int a = k, b = (k + 1) % 3, d = (k + 2) % 3;
-    const double daa = (double)dinv[(int64_t)a * n + i];
-    const double dab = (double)dinv[(int64_t)(k == 0 ? 3 : (k == 1 ? 4 : 5)) * n + i];
-    const double dad = (double)dinv[(int64_t)(k == 0 ? 5 : (k == 1 ? 3 : 4)) * n + i];
-    const double rv[3] = {r0, r1, r2};
-    const T v = (T)(daa * rv[a] + dab * rv[b] + dad * rv[d]);
-    if (own) z0[(int64_t)(c * 3 + k) * n + i] = v;
-    return v;
+  struct Raw {
+    T r[3], d[6];
+  };
+  struct ERaw {
+    T r[3];
+  };
+  __device__ void efetch(int c, int64_t i, ERaw& e) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.r[k] = r[(int64_t)(c * 3 + k) * n + i];
   }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, double&,
-                        double&) const {
+  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.r[k] = r[(int64_t)(c * 3 + k) * n + i];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) w.d[t] = dinv[(int64_t)t * n + i];
+  }
+  __device__ void finish(int c, int64_t i, int, int, int, bool own, const Raw& w,
+                         T (&v)[3]) const {
+    const T r0 = (T)((double)w.r[0] - scal[S_MEAN0 * 8 + c]);
+    const T r1 = (T)((double)w.r[1] - scal[S_MEAN1 * 8 + c]);
+    const T r2 = (T)((double)w.r[2] - scal[S_MEAN2 * 8 + c]);
+    // dinv planes: xx, yy, zz, xy, yz, xz
+    const T dxx = w.d[0], dyy = w.d[1], dzz = w.d[2], dxy = w.d[3], dyz = w.d[4], dxz = w.d[5];
+    v[0] = dxx * r0 + dxy * r1 + dxz * r2;
+    v[1] = dxy * r0 + dyy * r1 + dyz * r2;
+    v[2] = dxz * r0 + dyz * r1 + dzz * r2;
+    if (own)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) z0[(int64_t)(c * 3 + k) * n + i] = v[k];
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, const ERaw& e,
+                        double&, double&) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t o = (int64_t)(c * 3 + k) * n + i;
-      t[o] = (T)((double)r[o] - scal[(S_MEAN0 + k) * 8 + c]) - ku[k];
+      t[o] = (T)((double)e.r[k] - scal[(S_MEAN0 + k) * 8 + c]) - ku[k];
     }
   }
 };
 
-// z1 = z0 + P ec;  zout = z1 + D^-1 (r - K z1);  acc r.zout
+// Post-smoothing: zout = z1 + D^-1 ((r - m) - K z1), acc (r - m).zout.  z1 is
+// the pre-smoothed correction plus the prolongated coarse correction.
 template <typename T>
 struct OpPostSmooth {
   static constexpr int NACC = 1;
-  const T* z0;
-  const T* ec;
+  const T* z1;
   const T* r;
   const T* dinv;
   T* zout;
   int64_t n;
-  Grid gc;
   const double* scal;
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int gx, int gy, int gz, bool) const {
-    const int X0 = gx >> 1, Y0 = gy >> 1, Z0 = gz >> 1;
-    const int X1 = (gx & 1) ? (X0 + 1 == gc.nx ? 0 : X0 + 1) : X0;
-    const int Y1 = (gy & 1) ? (Y0 + 1 == gc.ny ? 0 : Y0 + 1) : Y0;
-    const int Z1 = (gz & 1) ? (Z0 + 1 == gc.nz ? 0 : Z0 + 1) : Z0;
-    const T wx = (gx & 1) ? T(0.5) : T(1), wy = (gy & 1) ? T(0.5) : T(1);
-    const T wz = (gz & 1) ? T(0.5) : T(1);
-    const T* e = ec + (int64_t)(c * 3 + k) * gc.n;
-    const int64_t cxy = (int64_t)gc.nx * gc.ny;
-    T v = e[X0 + (int64_t)gc.nx * Y0 + cxy * Z0];
-    if (gx & 1) v += e[X1 + (int64_t)gc.nx * Y0 + cxy * Z0];
-    if (gy & 1) {
-      v += e[X0 + (int64_t)gc.nx * Y1 + cxy * Z0];
-      if (gx & 1) v += e[X1 + (int64_t)gc.nx * Y1 + cxy * Z0];
-    }
-    if (gz & 1) {
-      T w = e[X0 + (int64_t)gc.nx * Y0 + cxy * Z1];
-      if (gx & 1) w += e[X1 + (int64_t)gc.nx * Y0 + cxy * Z1];
-      if (gy & 1) {
-        w += e[X0 + (int64_t)gc.nx * Y1 + cxy * Z1];
-        if (gx & 1) w += e[X1 + (int64_t)gc.nx * Y1 + cxy * Z1];
-      }
-      v += w;
-    }
-    // all taps along an odd axis carry 1/2; the sums above grouped them
-    return z0[(int64_t)(c * 3 + k) * n + i] + wx * wy * wz * v;
+  struct Raw {
+    T u[3];
+  };
+  struct ERaw {
+    T r[3], d[6];
+  };
+  __device__ void efetch(int c, int64_t i, ERaw& e) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.r[k] = r[(int64_t)(c * 3 + k) * n + i];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) e.d[t] = dinv[(int64_t)t * n + i];
   }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, double& a0,
-                        double&) const {
+  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.u[k] = z1[(int64_t)(c * 3 + k) * n + i];
+  }
+  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = w.u[k];
+  }
+  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin,
+                        const ERaw& e, double& a0, double&) const {
     T res[3], rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      rv[k] = (T)((double)r[(int64_t)(c * 3 + k) * n + i] - scal[(S_MEAN0 + k) * 8 + c]);
+      rv[k] = (T)((double)e.r[k] - scal[(S_MEAN0 + k) * 8 + c]);
       res[k] = rv[k] - ku[k];
     }
-    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
-    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
+    const T dxx = e.d[0], dyy = e.d[1], dzz = e.d[2], dxy = e.d[3], dyz = e.d[4], dxz = e.d[5];
     T zn[3];
     zn[0] = uin[0] + (dxx * res[0] + dxy * res[1] + dxz * res[2]);
     zn[1] = uin[1] + (dxy * res[0] + dyy * res[1] + dyz * res[2]);
@@ -451,11 +539,21 @@ struct OpForceResidual {
   Partials part;
   int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  __device__ T load(int c, int k, int64_t i, int, int, int, bool) const {
-    return x[(int64_t)(c * 3 + k) * n + i];
+  struct Raw {
+    T u[3];
+  };
+  struct ERaw {};
+  __device__ void efetch(int, int64_t, ERaw&) const {}
+  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.u[k] = x[(int64_t)(c * 3 + k) * n + i];
+  }
+  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = w.u[k];
   }
   __device__ void store(int c, int64_t i, int gx, int gy, int gz, const T* ku, const T*,
-                        double& a0, double& a1) const {
+                        const ERaw&, double& a0, double& a1) const {
     T f[3];
     forcing_at(g, s, tpl, c, gx, gy, gz, f);
 #pragma unroll
@@ -627,11 +725,11 @@ void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal) {
 }
 
 template <typename T>
-void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q,
+void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q, double* x,
                   const double* scal, Partials part, int* nblk_out) {
   // The new direction goes to a separate buffer: the kernel reads halo values of
   // pold that neighbouring blocks must not have overwritten yet.
-  OpMatvecP<T> op{z, pold, pnew, q, L.g.n, scal, part, S_PQ, 0};
+  OpMatvecP<T> op{z, pold, pnew, q, x, L.g.n, scal, part, S_PQ, 0};
   launch_op0(L, op);
   *nblk_out = tile_geom(L.g).ntiles;
 }
@@ -644,9 +742,9 @@ void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
 }
 
 template <typename T>
-void op0_post_smooth(const Op0Launch<T>& L, const T* z0, const T* ec, Grid gc, const T* r,
-                     const T* dinv, T* zout, const double* scal, Partials part, int* nblk_out) {
-  OpPostSmooth<T> op{z0, ec, r, dinv, zout, L.g.n, gc, scal, part, S_RZNEW, 0};
+void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
+                     const double* scal, Partials part, int* nblk_out) {
+  OpPostSmooth<T> op{z1, r, dinv, zout, L.g.n, scal, part, S_RZNEW, 0};
   launch_op0(L, op);
   *nblk_out = tile_geom(L.g).ntiles;
 }
@@ -689,12 +787,12 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
 
 #define HMG_INST(T)                                                                              \
   template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
-  template void op0_matvec_p<T>(const Op0Launch<T>&, const T*, const T*, T*, T*, const double*, \
-                                Partials, int*);                                                 \
+  template void op0_matvec_p<T>(const Op0Launch<T>&, const T*, const T*, T*, T*, double*,       \
+                                const double*, Partials, int*);                                  \
   template void op0_residual<T>(const Op0Launch<T>&, const T*, const T*, T*, T*,               \
                                 const double*);                                                  \
-  template void op0_post_smooth<T>(const Op0Launch<T>&, const T*, const T*, Grid, const T*,     \
-                                   const T*, T*, const double*, Partials, int*);                 \
+  template void op0_post_smooth<T>(const Op0Launch<T>&, const T*, const T*, const T*, T*,       \
+                                   const double*, Partials, int*);                               \
   template void op0_force_residual<T>(const Op0Launch<double>&, const LoadTpl<double>&,         \
                                       const double*, T*, const double*, Partials, int*);         \
   template void forcing<T>(const Grid&, const LoadTpl<double>&, const double*, T*, Partials,    \

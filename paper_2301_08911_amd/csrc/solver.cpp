@@ -372,13 +372,13 @@ class Solver final : public SolverIface {
     while (any(active) && it < max_iter) {
       ++it;
       const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T);
-      clock.timed(HMG_K_MATVEC, vn * (nact * 12 * TB + TB), st_, [&] {
-        op0_matvec_p<T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
+      clock.timed(HMG_K_MATVEC, vn * (nact * (12 * TB + (it > 1 ? 48 : 0)) + TB), st_, [&] {
+        op0_matvec_p<T>(L0, z_, pold, pnew, q_, x_, scal_, part_, &nb);
       });
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      clock.timed(HMG_K_UPDATE, vn * nact * (48 + 12 * TB), st_, [&] {
-        vec_update_xr<T>(g0, x_, r_, pnew, q_, scal_, part_, &nb, st_);
+      clock.timed(HMG_K_UPDATE, vn * nact * 9 * TB, st_, [&] {
+        vec_update_r<T>(g0, r_, q_, scal_, part_, &nb, st_);
       });
       fin_sum(part_, S_RR, nb, scal_, false, st_);
       fin_mean(part_, nb, g0.n, scal_, st_);
@@ -400,6 +400,7 @@ class Solver final : public SolverIface {
       if (anycheck) {
         // Confirm on the residual f - K x recomputed in FP64 before a case
         // stops; the recomputed residual also replaces the recursive one.
+        vec_flush_x<T>(g0, x_, pold, scal_, st_);  // pold now holds this iteration's p
         set_mask(aux_, check);
         clock.timed(HMG_K_TRUE_RESIDUAL, (double)g0.n * (count(check) * (24 + 3 * sizeof(T)) + 8),
                     st_, [&] { op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb); });
@@ -430,7 +431,8 @@ class Solver final : public SolverIface {
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
       fin_beta(scal_, st_);
     }
-    // Zero-mean solution and the recomputed final residual of every case.
+    // Pending iterate updates, zero-mean solution, recomputed final residuals.
+    vec_flush_x<T>(g0, x_, pold, scal_, st_);
     vec_mean_partial<double>(g0, x_, part_, &nb, st_);
     fin_mean(part_, nb, g0.n, aux_, st_);
     vec_mean_subtract<double>(g0, x_, aux_, st_);
@@ -632,8 +634,9 @@ class Solver final : public SolverIface {
                 [&] { op0_residual<T>(L0, r0, dinv0_, q_, t_, scal); });
     restrict_to<T>(g0, grids_[1], t_, lev_[1].r, scal, st_);
     descend(1, scal);
-    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 9.375 * TB + 7 * TB), st_, [&] {
-      op0_post_smooth<T>(L0, q_, lev_[1].z, grids_[1], r0, dinv0_, zout, scal, part_, nb);
+    prolong_add<T>(g0, grids_[1], q_, lev_[1].z, scal, false, st_);
+    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 9 * TB + 7 * TB), st_, [&] {
+      op0_post_smooth<T>(L0, q_, r0, dinv0_, zout, scal, part_, nb);
     });
     return check_hip("vcycle");
   }

@@ -51,20 +51,19 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
     }
 }
 
-// x (FP64) += alpha p; r -= alpha q; partials of ||r||^2 and of sum(r) per
-// case and component (the translation component removed before smoothing).
+// r -= alpha q; partials of ||r||^2 and of sum(r) per case and component (the
+// translation component is removed before smoothing).
 template <typename T>
-__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
-                                                    T* __restrict__ r, const T* __restrict__ p,
+__global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ r,
                                                     const T* __restrict__ q, const double* scal,
                                                     Partials part) {
   __shared__ double red[(VB / 64) * NCASE * 4];
   bool on[NCASE];
-  double al[NCASE];
+  T al[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) {
     on[c] = case_on(scal, c);
-    al[c] = scal[S_ALPHA * 8 + c];
+    al[c] = (T)scal[S_ALPHA * 8 + c];
   }
   double acc[NCASE * 4];  // [c]: ||r||^2, [6 + 3c + k]: sum r
 #pragma unroll
@@ -78,8 +77,7 @@ __global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t o = (int64_t)(c * 3 + k) * n + i;
-        x[o] = x[o] + al[c] * (double)p[o];
-        const T rv = r[o] - (T)al[c] * q[o];
+        const T rv = r[o] - al[c] * q[o];
         r[o] = rv;
         acc[c] += (double)rv * (double)rv;
         acc[NCASE + 3 * c + k] += (double)rv;
@@ -95,6 +93,31 @@ __global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__
       for (int k = 0; k < 3; ++k)
         part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = acc[NCASE + 3 * c + k];
     }
+}
+
+// x += alpha_x p for every case with a pending step (slot S_XALPHA).
+template <typename T>
+__global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict__ x,
+                                                     const T* __restrict__ p, const double* scal) {
+  double ax[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) ax[c] = scal[S_XALPHA * 8 + c];
+  const int64_t n = g.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      if (ax[c] == 0.0) continue;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int64_t o = (int64_t)(c * 3 + k) * n + i;
+        x[o] += ax[c] * (double)p[o];
+      }
+    }
+}
+
+__global__ void clear_xalpha_kernel(double* scal) {
+  if (threadIdx.x < 8) scal[S_XALPHA * 8 + threadIdx.x] = 0.0;
 }
 
 // z = Dinv (r - m), m the per-component mean in `mean` (slots S_MEAN*, may be NULL).
@@ -246,6 +269,7 @@ __global__ void fin_init_kernel(double* scal, double eps_abs, double tol) {
   scal[S_ALPHA * 8 + c] = 0.0;
   scal[S_BETA * 8 + c] = 0.0;
   scal[S_RZ * 8 + c] = 0.0;
+  scal[S_XALPHA * 8 + c] = 0.0;
 }
 
 __global__ void fin_alpha_kernel(double* scal) {
@@ -253,7 +277,9 @@ __global__ void fin_alpha_kernel(double* scal) {
   if (c >= NCASE) return;
   const double pq = scal[S_PQ * 8 + c];
   const bool on = scal[S_ACTIVE * 8 + c] != 0.0 && pq != 0.0;
-  scal[S_ALPHA * 8 + c] = on ? scal[S_RZ * 8 + c] / pq : 0.0;
+  const double a = on ? scal[S_RZ * 8 + c] / pq : 0.0;
+  scal[S_ALPHA * 8 + c] = a;
+  scal[S_XALPHA * 8 + c] = a;  // applied to x by the next matvec or a flush
 }
 
 __global__ void fin_beta_kernel(double* scal) {
@@ -284,6 +310,7 @@ __global__ void all_active_kernel(double* scal) {
     scal[S_BETA * 8 + c] = 0.0;
     scal[S_ALPHA * 8 + c] = 0.0;
     scal[S_RESTART * 8 + c] = 0.0;
+    scal[S_XALPHA * 8 + c] = 0.0;
   }
 }
 
@@ -326,10 +353,16 @@ template void vec_convert<double, float>(float*, const double*, int64_t, hipStre
 template void vec_convert<double, double>(double*, const double*, int64_t, hipStream_t);
 
 template <typename T>
-void vec_update_xr(const Grid& g, double* x, T* r, const T* p, const T* q, const double* scal,
-                   Partials part, int* nblk_out, hipStream_t st) {
+void vec_flush_x(const Grid& g, double* x, const T* p, double* scal, hipStream_t st) {
+  hipLaunchKernelGGL(flush_x_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, x, p, scal);
+  hipLaunchKernelGGL(clear_xalpha_kernel, dim3(1), dim3(64), 0, st, scal);
+}
+
+template <typename T>
+void vec_update_r(const Grid& g, T* r, const T* q, const double* scal, Partials part,
+                  int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, x, r, p, q, scal, part);
+  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, r, q, scal, part);
   *nblk_out = nb;
 }
 template <typename T>
@@ -397,8 +430,9 @@ void scal_set_all_active(double* scal, hipStream_t st) {
 }
 
 #define HMG_INST(T)                                                                             \
-  template void vec_update_xr<T>(const Grid&, double*, T*, const T*, const T*, const double*,   \
-                                 Partials, int*, hipStream_t);                                  \
+  template void vec_update_r<T>(const Grid&, T*, const T*, const double*, Partials, int*,        \
+                                hipStream_t);                                                   \
+  template void vec_flush_x<T>(const Grid&, double*, const T*, double*, hipStream_t);           \
   template void vec_jacobi0<T>(const Grid&, const T*, const T*, T*, const double*,              \
                                const double*, hipStream_t);                                     \
   template void vec_fill<T>(T*, int64_t, T, hipStream_t);                                       \
