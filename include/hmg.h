@@ -62,13 +62,25 @@ typedef enum {
 typedef enum {
   HMG_FP64 = 0,        /* all fields, stencils and reductions in double        */
   HMG_FP32 = 1,        /* float fields/stencils, FP64 dots and coarsest solve  */
-  HMG_MIXED_BF16 = 2,  /* reserved: bf16 streamed operands (not yet built)     */
-  HMG_MIXED_FP16 = 3   /* reserved: fp16 streamed operands (not yet built)     */
+  HMG_MIXED_BF16 = 2,  /* Sec. 5 mixed precision: the multigrid preconditioner
+                          streams its vectors (smoother corrections, coarse
+                          residuals and corrections) in bf16 and computes in
+                          FP32; outer PCG vectors FP32, iterate FP64, FP64
+                          dots, residual recomputation (replace_every) and
+                          coarsest solve; coarse stencils FP32                */
+  HMG_MIXED_FP16 = 3,  /* reserved, not built: fp16 vectors cannot hold the
+                          smoother corrections of soft regions (1/Emin scale)  */
+  HMG_MIXED_BF16_STENCIL = 4 /* HMG_MIXED_BF16 with the coarse stencils and
+                          block inverses also in bf16.  Rounding the stencils
+                          (2^-8) perturbs the near-null-space of the coarse
+                          operators; on high-contrast cells (Emin = 1e-9 with
+                          void) MG-PCG can then stagnate near 1e-2            */
 } hmg_precision;
 
 /* Solver configuration (Sec. 6 defaults: E0 = 1, nu = 0.3, p = 3). */
 typedef struct hmg_config {
-  int32_t nx, ny, nz;     /* cells per axis, each >= 4                        */
+  int32_t nx, ny, nz;     /* cells per axis, each >= 4; nx*ny <= 2^27,         */
+                          /* nx*ny*nz <= 2^31                                  */
   double E0;              /* Young's modulus of the solid (> 0)               */
   double nu;              /* Poisson ratio, in (-1, 0.5)                      */
   double penal;           /* SIMP exponent p (>= 1)                           */
@@ -88,7 +100,7 @@ typedef struct hmg_config {
  * hipStream_t (NULL = default stream).  Allocates the multigrid hierarchy and
  * the PCG work fields in device memory.  Fails with HMG_E_INVALID for a bad
  * configuration (shape, material, levels, or a coarsest grid above the direct
- * solver's limit of 6144 unknowns) and HMG_E_OOM if the device is too small. */
+ * solver's limit of 3072 unknowns) and HMG_E_OOM if the device is too small. */
 hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out);
 
 /* Release every device buffer of the context.  NULL is accepted. */
@@ -160,10 +172,11 @@ const char* hmg_last_error(hmg_ctx ctx);
 /* Kernels whose launches inside hmg_solve_cases can be timed. */
 typedef enum {
   HMG_K_MATVEC = 0,        /* p = z + beta p, q = K p, p.q          (level-0 operator) */
-  HMG_K_RESIDUAL = 1,      /* z0 = D^-1 (r - m), t = (r - m) - K z0  (level-0 operator) */
+  HMG_K_RESIDUAL = 1,      /* t = (r - m) - K z0                    (level-0 operator) */
   HMG_K_POST_SMOOTH = 2,   /* z = z1 + D^-1 ((r - m) - K z1), z1 = z0 + P e            */
   HMG_K_UPDATE = 3,        /* x += alpha p (FP64), r -= alpha q                          */
-  HMG_K_TRUE_RESIDUAL = 4  /* r = f - K x in FP64                                        */
+  HMG_K_TRUE_RESIDUAL = 4, /* r = f - K x in FP64                                        */
+  HMG_K_JACOBI = 5         /* z0 = D^-1 (r - m), level 0, all cases per vertex           */
 } hmg_kernel;
 
 /* enable != 0 clears the counters and starts recording a HIP event pair around

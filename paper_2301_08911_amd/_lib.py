@@ -11,6 +11,12 @@ SYMBOLS = (
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
     "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
     "hmg_load_vectors", "hmg_vcycle", "hmg_transfer", "hmg_profile", "hmg_profile_read",
+    # include/hmg_nn.h
+    "hmg_nn_create", "hmg_nn_destroy", "hmg_nn_param_count", "hmg_nn_get_params",
+    "hmg_nn_set_params", "hmg_nn_get_grads", "hmg_nn_forward", "hmg_nn_backward",
+    "hmg_nn_zero_grad", "hmg_nn_adam_step", "hmg_nn_mse", "hmg_warm_start",
+    "hmg_conv3d_forward", "hmg_conv3d_backward_data", "hmg_conv3d_backward_weight",
+    "hmg_conv3d_workspace",
 )
 
 
@@ -23,6 +29,12 @@ class HmgConfig(ctypes.Structure):
         ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("replace_every", ctypes.c_int32),
     ]
+
+
+class HmgNnConfig(ctypes.Structure):
+    """Mirror of ``hmg_nn_config`` in include/hmg_nn.h."""
+    _fields_ = [("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32),
+                ("in_channels", ctypes.c_int32), ("out_channels", ctypes.c_int32)]
 
 
 _lib = None
@@ -38,7 +50,7 @@ def load() -> ctypes.CDLL:
             f"{LIB_PATH} is missing: build it with `python -m paper_2301_08911_amd.build` "
             "(the solver has no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
-    vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    vp, i32, f64, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_int64
     P = ctypes.POINTER
     sig = {
         "hmg_create": ([P(HmgConfig), vp, P(vp)], i32),
@@ -61,6 +73,23 @@ def load() -> ctypes.CDLL:
         "hmg_transfer": ([vp, i32, i32, vp, vp], i32),
         "hmg_profile": ([vp, i32], i32),
         "hmg_profile_read": ([vp, i32, P(ctypes.c_int64), P(f64), P(f64)], i32),
+        "hmg_nn_create": ([P(HmgNnConfig), vp, ctypes.c_uint64, P(vp)], i32),
+        "hmg_nn_destroy": ([vp], i32),
+        "hmg_nn_param_count": ([vp, P(i64)], i32),
+        "hmg_nn_get_params": ([vp, vp, i64], i32),
+        "hmg_nn_set_params": ([vp, vp, i64], i32),
+        "hmg_nn_get_grads": ([vp, vp, i64], i32),
+        "hmg_nn_forward": ([vp, vp, i32, i32, vp], i32),
+        "hmg_nn_backward": ([vp, vp], i32),
+        "hmg_nn_zero_grad": ([vp], i32),
+        "hmg_nn_adam_step": ([vp, f64, f64, f64, f64, i32], i32),
+        "hmg_nn_mse": ([vp, vp, vp, i64, vp, P(f64)], i32),
+        "hmg_warm_start": ([vp, vp, f64, P(f64), P(i32)], i32),
+        "hmg_conv3d_forward": ([vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, i32], i32),
+        "hmg_conv3d_backward_data": ([vp, vp, vp, vp, i32, i32, i32, i32, i32, i32], i32),
+        "hmg_conv3d_backward_weight": ([vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32],
+                                       i32),
+        "hmg_conv3d_workspace": ([i32, i32, i32, i32, i32, i32], i64),
     }
     for name, (args, ret) in sig.items():
         fn = getattr(lib, name)

@@ -25,16 +25,27 @@ inline int pw_blocks(int64_t n, int tpb, int cap) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Conversions between the storage type and FP64 / the arithmetic type.
+template <typename T>
+__device__ __forceinline__ double to_d(T v) {
+  return (double)(typename Acc<T>::type)v;
+}
+template <typename T>
+__device__ __forceinline__ T from_d(double v) {
+  return (T)(typename Acc<T>::type)v;
+}
+
 __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
 
 // MODE 0: out = K u.  MODE 1: out = (r - m) - K u.  MODE 2: out = u + Dinv ((r - m) - K u).
 // m is the per-component mean of r (slots S_MEAN* of `mean`, FP64).
-template <typename T, int MODE>
-__global__ void stencil_kernel(Grid g, const T* __restrict__ st, const T* __restrict__ u,
-                               const T* __restrict__ r, const T* __restrict__ dinv,
+template <typename T, typename W, int MODE>
+__global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u,
+                               const T* __restrict__ r, const W* __restrict__ dinv,
                                T* __restrict__ out, const double* scal, const double* mean) {
+  using A = typename Acc<T>::type;
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
@@ -47,54 +58,53 @@ __global__ void stencil_kernel(Grid g, const T* __restrict__ st, const T* __rest
     int xs[3] = {gx == 0 ? g.nx - 1 : gx - 1, gx, gx + 1 == g.nx ? 0 : gx + 1};
     int ys[3] = {gy == 0 ? g.ny - 1 : gy - 1, gy, gy + 1 == g.ny ? 0 : gy + 1};
     int zs[3] = {gz == 0 ? g.nz - 1 : gz - 1, gz, gz + 1 == g.nz ? 0 : gz + 1};
-    T acc[NCASE][3];
+    A acc[NCASE][3];
 #pragma unroll
-    for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = T(0);
+    for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
     for (int d = 0; d < 27; ++d) {
       const int dx = d % 3, dy = (d / 3) % 3, dz = d / 9;
       const int64_t w = xs[dx] + (int64_t)g.nx * (ys[dy] + (int64_t)g.ny * zs[dz]);
-      T K[9];
+      A K[9];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) K[t] = st[(int64_t)(d * 9 + t) * n + i];
+      for (int t = 0; t < 9; ++t) K[t] = (A)st[(int64_t)(d * 9 + t) * n + i];
 #pragma unroll
       for (int c = 0; c < NCASE; ++c) {
         if (!on[c]) continue;
-        const T u0 = u[(int64_t)(c * 3 + 0) * n + w];
-        const T u1 = u[(int64_t)(c * 3 + 1) * n + w];
-        const T u2 = u[(int64_t)(c * 3 + 2) * n + w];
+        const A u0 = (A)u[(int64_t)(c * 3 + 0) * n + w];
+        const A u1 = (A)u[(int64_t)(c * 3 + 1) * n + w];
+        const A u2 = (A)u[(int64_t)(c * 3 + 2) * n + w];
         acc[c][0] += K[0] * u0 + K[1] * u1 + K[2] * u2;
         acc[c][1] += K[3] * u0 + K[4] * u1 + K[5] * u2;
         acc[c][2] += K[6] * u0 + K[7] * u1 + K[8] * u2;
       }
     }
-    T D[6];
+    A D[6];
     if (MODE == 2) {
 #pragma unroll
-      for (int t = 0; t < 6; ++t) D[t] = dinv[(int64_t)t * n + i];
+      for (int t = 0; t < 6; ++t) D[t] = (A)dinv[(int64_t)t * n + i];
     }
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
       if (MODE == 0) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = acc[c][k];
+        for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = (T)acc[c][k];
       } else {
-        T res[3];
+        A res[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          res[k] = (T)((double)r[(int64_t)(c * 3 + k) * n + i] - mean[(S_MEAN0 + k) * 8 + c]) -
+          res[k] = (A)(to_d(r[(int64_t)(c * 3 + k) * n + i]) - mean[(S_MEAN0 + k) * 8 + c]) -
                    acc[c][k];
         if (MODE == 1) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = res[k];
+          for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = (T)res[k];
         } else {
-          const T* uu = u;
-          const T z0 = uu[(int64_t)(c * 3 + 0) * n + i] + (D[0] * res[0] + D[3] * res[1] + D[5] * res[2]);
-          const T z1 = uu[(int64_t)(c * 3 + 1) * n + i] + (D[3] * res[0] + D[1] * res[1] + D[4] * res[2]);
-          const T z2 = uu[(int64_t)(c * 3 + 2) * n + i] + (D[5] * res[0] + D[4] * res[1] + D[2] * res[2]);
-          out[(int64_t)(c * 3 + 0) * n + i] = z0;
-          out[(int64_t)(c * 3 + 1) * n + i] = z1;
-          out[(int64_t)(c * 3 + 2) * n + i] = z2;
+          const A z0 = (A)u[(int64_t)(c * 3 + 0) * n + i] + (D[0] * res[0] + D[3] * res[1] + D[5] * res[2]);
+          const A z1 = (A)u[(int64_t)(c * 3 + 1) * n + i] + (D[3] * res[0] + D[1] * res[1] + D[4] * res[2]);
+          const A z2 = (A)u[(int64_t)(c * 3 + 2) * n + i] + (D[5] * res[0] + D[4] * res[1] + D[2] * res[2]);
+          out[(int64_t)(c * 3 + 0) * n + i] = (T)z0;
+          out[(int64_t)(c * 3 + 1) * n + i] = (T)z1;
+          out[(int64_t)(c * 3 + 2) * n + i] = (T)z2;
         }
       }
     }
@@ -108,6 +118,7 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* _
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  using A = typename Acc<T>::type;
   for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < gc.n;
        I += (int64_t)gridDim.x * blockDim.x) {
     const int X = (int)(I % gc.nx);
@@ -116,32 +127,32 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* _
     int xs[3] = {modp(2 * X - 1, gf.nx), 2 * X, 2 * X + 1};
     int ys[3] = {modp(2 * Y - 1, gf.ny), 2 * Y, 2 * Y + 1};
     int zs[3] = {modp(2 * Z - 1, gf.nz), 2 * Z, 2 * Z + 1};
-    T acc[NCASE][3];
+    A acc[NCASE][3];
 #pragma unroll
-    for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = T(0);
+    for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
     for (int a = 0; a < 27; ++a) {
       const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-      const T w = T((ax == 1 ? 1.0 : 0.5) * (ay == 1 ? 1.0 : 0.5) * (az == 1 ? 1.0 : 0.5));
+      const A w = A((ax == 1 ? 1.0 : 0.5) * (ay == 1 ? 1.0 : 0.5) * (az == 1 ? 1.0 : 0.5));
       const int64_t f = xs[ax] + (int64_t)gf.nx * (ys[ay] + (int64_t)gf.ny * zs[az]);
 #pragma unroll
       for (int c = 0; c < NCASE; ++c) {
         if (!on[c]) continue;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[c][k] += w * tf[(int64_t)(c * 3 + k) * gf.n + f];
+        for (int k = 0; k < 3; ++k) acc[c][k] += w * (A)tf[(int64_t)(c * 3 + k) * gf.n + f];
       }
     }
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) rc[(int64_t)(c * 3 + k) * gc.n + I] = acc[c][k];
+      for (int k = 0; k < 3; ++k) rc[(int64_t)(c * 3 + k) * gc.n + I] = (T)acc[c][k];
     }
   }
 }
 
 // zf[v] (+)= sum over the coarse vertices of v's cell of trilinear weights * ec
-template <typename T>
-__global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const T* __restrict__ ec,
+template <typename T, typename C>
+__global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __restrict__ ec,
                                const double* scal, int overwrite) {
   bool on[NCASE];
 #pragma unroll
@@ -155,8 +166,9 @@ __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const T* __
     const int X1 = (gx & 1) ? (X0 + 1 == gc.nx ? 0 : X0 + 1) : X0;
     const int Y1 = (gy & 1) ? (Y0 + 1 == gc.ny ? 0 : Y0 + 1) : Y0;
     const int Z1 = (gz & 1) ? (Z0 + 1 == gc.nz ? 0 : Z0 + 1) : Z0;
+    using A = typename Acc<T>::type;
     const int nt = 1 << ((gx & 1) + (gy & 1) + (gz & 1));
-    const T w = T(1.0) / T(nt);
+    const A w = A(1.0) / A(nt);
     int64_t idx[8];
     int m = 0;
     for (int cz = 0; cz < ((gz & 1) ? 2 : 1); ++cz)
@@ -168,11 +180,11 @@ __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const T* __
       if (!on[c]) continue;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const T* e = ec + (int64_t)(c * 3 + k) * gc.n;
-        T v = T(0);
-        for (int t = 0; t < m; ++t) v += e[idx[t]];
+        const C* e = ec + (int64_t)(c * 3 + k) * gc.n;
+        A v = A(0);
+        for (int t = 0; t < m; ++t) v += (A)e[idx[t]];
         T* o = zf + (int64_t)(c * 3 + k) * gf.n + i;
-        *o = overwrite ? w * v : *o + w * v;
+        *o = (T)(overwrite ? w * v : (A)*o + w * v);
       }
     }
   }
@@ -181,8 +193,8 @@ __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const T* __
 // First coarse level from the densities.  Coarse vertex V is local node A of
 // the coarse element with origin V - A; that element holds the 8 fine elements
 // 2(V - A) + sigma, each contributing s * (W_sigma^T K0 W_sigma)[A, A + D].
-template <typename T>
-__global__ void galerkin_first_kernel(Grid gf, Grid gc, const T* __restrict__ s,
+template <typename S, typename T>
+__global__ void galerkin_first_kernel(Grid gf, Grid gc, const S* __restrict__ s,
                                       const double* __restrict__ msig, T* __restrict__ st) {
   const int d = blockIdx.y;
   const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
@@ -211,7 +223,7 @@ __global__ void galerkin_first_kernel(Grid gf, Grid gc, const T* __restrict__ s,
       }
     }
 #pragma unroll
-    for (int t = 0; t < 9; ++t) st[(int64_t)(d * 9 + t) * gc.n + V] = (T)blk[t];
+    for (int t = 0; t < 9; ++t) st[(int64_t)(d * 9 + t) * gc.n + V] = from_d<T>(blk[t]);
   }
 }
 
@@ -239,11 +251,11 @@ __global__ void galerkin_next_kernel(Grid gf, Grid gc, const T* __restrict__ stf
         const double w = wa * (bx ? 0.5 : 1.0) * (by ? 0.5 : 1.0) * (bz ? 0.5 : 1.0);
         const int dp = (px + 1) + 3 * (py + 1) + 9 * (pz + 1);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) blk[t] += w * (double)stf[(int64_t)(dp * 9 + t) * gf.n + i];
+        for (int t = 0; t < 9; ++t) blk[t] += w * to_d(stf[(int64_t)(dp * 9 + t) * gf.n + i]);
       }
     }
 #pragma unroll
-    for (int t = 0; t < 9; ++t) stc[(int64_t)(d * 9 + t) * gc.n + V] = (T)blk[t];
+    for (int t = 0; t < 9; ++t) stc[(int64_t)(d * 9 + t) * gc.n + V] = from_d<T>(blk[t]);
   }
 }
 
@@ -255,19 +267,19 @@ __global__ void dinv_stencil_kernel(Grid g, const T* __restrict__ st, double ome
        i += (int64_t)gridDim.x * blockDim.x) {
     double a[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) a[t] = (double)st[(int64_t)(13 * 9 + t) * g.n + i];
+    for (int t = 0; t < 9; ++t) a[t] = to_d(st[(int64_t)(13 * 9 + t) * g.n + i]);
     const double a00 = a[0], a11 = a[4], a22 = a[8];
     const double a01 = 0.5 * (a[1] + a[3]), a12 = 0.5 * (a[5] + a[7]), a02 = 0.5 * (a[2] + a[6]);
     const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22;
     const double c02 = a01 * a12 - a02 * a11, c11 = a00 * a22 - a02 * a02;
     const double c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
     const double f = omega / (a00 * c00 + a01 * c01 + a02 * c02);
-    dinv[i] = (T)(f * c00);
-    dinv[g.n + i] = (T)(f * c11);
-    dinv[2 * g.n + i] = (T)(f * c22);
-    dinv[3 * g.n + i] = (T)(f * c01);
-    dinv[4 * g.n + i] = (T)(f * c12);
-    dinv[5 * g.n + i] = (T)(f * c02);
+    dinv[i] = from_d<T>(f * c00);
+    dinv[g.n + i] = from_d<T>(f * c11);
+    dinv[2 * g.n + i] = from_d<T>(f * c22);
+    dinv[3 * g.n + i] = from_d<T>(f * c01);
+    dinv[4 * g.n + i] = from_d<T>(f * c12);
+    dinv[5 * g.n + i] = from_d<T>(f * c02);
   }
 }
 
@@ -288,7 +300,7 @@ __global__ void dense_kernel(Grid g, const T* __restrict__ st, double* __restric
                         (int64_t)g.nx * (modp(gy + dy, g.ny) + (int64_t)g.ny * modp(gz + dz, g.nz));
       for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 3; ++q)
-          A[(3 * v + p) * N + 3 * w + q] += (double)st[(int64_t)(d * 9 + p * 3 + q) * g.n + v];
+          A[(3 * v + p) * N + 3 * w + q] += to_d(st[(int64_t)(d * 9 + p * 3 + q) * g.n + v]);
     }
   }
 }
@@ -346,9 +358,9 @@ __device__ double block_allsum(double v, double* lds) {
 
 // One workgroup per case: project the RHS to zero mean per component, apply
 // the inverse of the vertex-0-pinned matrix, project the result to zero mean.
-template <typename T>
+template <typename R, typename T>
 __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double* __restrict__ Ainv,
-                                                            const T* __restrict__ r, T* __restrict__ z,
+                                                            const R* __restrict__ r, T* __restrict__ z,
                                                             const double* scal) {
   extern __shared__ double sh[];
   __shared__ double red[16];
@@ -361,7 +373,7 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
   for (int k = 0; k < 3; ++k) {
     double a = 0.0;
     for (int v = threadIdx.x; v < n; v += blockDim.x) {
-      const double x = (double)r[(int64_t)(c * 3 + k) * n + v];
+      const double x = to_d(r[(int64_t)(c * 3 + k) * n + v]);
       rl[3 * v + k] = x;
       a += x;
     }
@@ -383,28 +395,28 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
   }
   for (int k = 0; k < 3; ++k)
     for (int v = threadIdx.x; v < n; v += blockDim.x)
-      z[(int64_t)(c * 3 + k) * n + v] = (T)(zl[3 * v + k] - m[k]);
+      z[(int64_t)(c * 3 + k) * n + v] = from_d<T>(zl[3 * v + k] - m[k]);
 }
 
 }  // namespace
 
-template <typename T>
-void kc_apply(const Grid& g, const T* st, const T* u, T* y, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, 0>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, u, (const T*)nullptr, (const T*)nullptr, y, (const double*)nullptr,
+template <typename T, typename W>
+void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s) {
+  hipLaunchKernelGGL((stencil_kernel<T, W, 0>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+                     g, st, u, (const T*)nullptr, (const W*)nullptr, y, (const double*)nullptr,
                      (const double*)nullptr);
 }
-template <typename T>
-void kc_residual(const Grid& g, const T* st, const T* z, const T* r, T* t, const double* scal,
+template <typename T, typename W>
+void kc_residual(const Grid& g, const W* st, const T* z, const T* r, T* t, const double* scal,
                  const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, 1>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, z, r, (const T*)nullptr, t, scal, mean);
+  hipLaunchKernelGGL((stencil_kernel<T, W, 1>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+                     g, st, z, r, (const W*)nullptr, t, scal, mean);
 }
-template <typename T>
-void kc_smooth(const Grid& g, const T* st, const T* z, const T* r, const T* dinv, T* zout,
+template <typename T, typename W>
+void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv, T* zout,
                const double* scal, const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, 2>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s, g,
-                     st, z, r, dinv, zout, scal, mean);
+  hipLaunchKernelGGL((stencil_kernel<T, W, 2>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+                     g, st, z, r, dinv, zout, scal, mean);
 }
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
@@ -412,16 +424,16 @@ void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const doubl
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(pw_blocks(gc.n, 256, 8192)), dim3(256), 0, s, gf, gc,
                      tf, rc, scal);
 }
-template <typename T>
-void prolong_add(const Grid& gf, const Grid& gc, T* zf, const T* ec, const double* scal,
+template <typename T, typename C>
+void prolong_add(const Grid& gf, const Grid& gc, T* zf, const C* ec, const double* scal,
                  bool overwrite, hipStream_t s) {
-  hipLaunchKernelGGL(prolong_kernel<T>, dim3(pw_blocks(gf.n, 256, 8192)), dim3(256), 0, s, gf, gc,
+  hipLaunchKernelGGL((prolong_kernel<T, C>), dim3(pw_blocks(gf.n, 256, 8192)), dim3(256), 0, s, gf, gc,
                      zf, ec, scal, overwrite ? 1 : 0);
 }
-template <typename T>
-void galerkin_first(const Grid& gf, const Grid& gc, const T* s, const double* msig_dev, T* st,
+template <typename S, typename T>
+void galerkin_first(const Grid& gf, const Grid& gc, const S* s, const double* msig_dev, T* st,
                     hipStream_t stm) {
-  hipLaunchKernelGGL(galerkin_first_kernel<T>, dim3(pw_blocks(gc.n, 256, 4096), 27), dim3(256), 0,
+  hipLaunchKernelGGL((galerkin_first_kernel<S, T>), dim3(pw_blocks(gc.n, 256, 4096), 27), dim3(256), 0,
                      stm, gf, gc, s, msig_dev, st);
 }
 template <typename T>
@@ -444,31 +456,51 @@ void gauss_jordan_inverse(int N, double* A, hipStream_t stm) {
   // scratch column lives right after the matrix (allocated by the caller)
   hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(1024), 0, stm, N, A, A + (int64_t)N * N);
 }
-template <typename T>
-void coarse_solve(const Grid& g, const double* Ainv, const T* r, T* z, const double* scal,
+template <typename R, typename T>
+void coarse_solve(const Grid& g, const double* Ainv, const R* r, T* z, const double* scal,
                   hipStream_t stm) {
   const size_t shm = sizeof(double) * 6 * g.n;
-  hipLaunchKernelGGL(coarse_solve_kernel<T>, dim3(NCASE), dim3(1024), shm, stm, g, Ainv, r, z, scal);
+  hipLaunchKernelGGL((coarse_solve_kernel<R, T>), dim3(NCASE), dim3(1024), shm, stm, g, Ainv, r, z,
+                     scal);
 }
 
+#define HMG_INSTKC(T, W)                                                                         \
+  template void kc_apply<T, W>(const Grid&, const W*, const T*, T*, hipStream_t);                 \
+  template void kc_residual<T, W>(const Grid&, const W*, const T*, const T*, T*, const double*,   \
+                                  const double*, hipStream_t);                                      \
+  template void kc_smooth<T, W>(const Grid&, const W*, const T*, const T*, const W*, T*,          \
+                                const double*, const double*, hipStream_t);
+HMG_INSTKC(float, float)
+HMG_INSTKC(double, double)
+HMG_INSTKC(bf16, bf16)
+HMG_INSTKC(bf16, float)
+#undef HMG_INSTKC
 #define HMG_INST(T)                                                                               \
-  template void kc_apply<T>(const Grid&, const T*, const T*, T*, hipStream_t);                    \
-  template void kc_residual<T>(const Grid&, const T*, const T*, const T*, T*, const double*,      \
-                               const double*, hipStream_t);                                         \
-  template void kc_smooth<T>(const Grid&, const T*, const T*, const T*, const T*, T*,             \
-                             const double*, const double*, hipStream_t);                            \
   template void restrict_to<T>(const Grid&, const Grid&, const T*, T*, const double*, hipStream_t); \
-  template void prolong_add<T>(const Grid&, const Grid&, T*, const T*, const double*, bool,       \
+  template void prolong_add<T, T>(const Grid&, const Grid&, T*, const T*, const double*, bool,    \
                                hipStream_t);                                                        \
-  template void galerkin_first<T>(const Grid&, const Grid&, const T*, const double*, T*,          \
-                                  hipStream_t);                                                     \
   template void galerkin_next<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);            \
   template void dinv_from_stencil<T>(const Grid&, const T*, double, T*, hipStream_t);             \
   template void dense_from_stencil<T>(const Grid&, const T*, double*, hipStream_t);               \
-  template void coarse_solve<T>(const Grid&, const double*, const T*, T*, const double*,          \
-                                hipStream_t);
+  template void coarse_solve<T, T>(const Grid&, const double*, const T*, T*, const double*,       \
+                                   hipStream_t);
 HMG_INST(float)
 HMG_INST(double)
+HMG_INST(bf16)
 #undef HMG_INST
+template void galerkin_first<float, float>(const Grid&, const Grid&, const float*, const double*,
+                                           float*, hipStream_t);
+template void galerkin_first<double, double>(const Grid&, const Grid&, const double*,
+                                             const double*, double*, hipStream_t);
+template void prolong_add<bf16, float>(const Grid&, const Grid&, bf16*, const float*,
+                                       const double*, bool, hipStream_t);
+template void coarse_solve<bf16, float>(const Grid&, const double*, const bf16*, float*,
+                                        const double*, hipStream_t);
+template void prolong_add<float, bf16>(const Grid&, const Grid&, float*, const bf16*,
+                                       const double*, bool, hipStream_t);
+template void coarse_solve<float, bf16>(const Grid&, const double*, const float*, bf16*,
+                                        const double*, hipStream_t);
+template void galerkin_first<float, bf16>(const Grid&, const Grid&, const float*, const double*,
+                                          bf16*, hipStream_t);
 
 }  // namespace hmg

@@ -11,6 +11,23 @@ namespace hmg {
 
 constexpr int NCASE = 6;  // six unit macro strains (Voigt 11,22,33,12,23,13)
 
+// Storage of the multigrid preconditioner's streamed data (smoother
+// corrections, coarse residuals and corrections, coarse stencils and block
+// inverses): V is the type in memory, Acc<V> the type the kernels compute in.
+// The reduced-precision form stores V = bf16 and computes in FP32; the plain
+// forms store what they compute in.  The outer PCG vectors keep the
+// arithmetic type.
+using bf16 = __bf16;
+using f16 = _Float16;
+template <typename V>
+struct Acc {
+  using type = float;
+};
+template <>
+struct Acc<double> {
+  using type = double;
+};
+
 // Periodic grid of one multigrid level: n vertices == n elements.
 struct Grid {
   int nx = 0, ny = 0, nz = 0;
@@ -70,7 +87,8 @@ enum Slot {
   S_MEAN2,
   S_TRUE,       // recomputed ||f - K x||^2
   S_RESTART,    // 1: the residual was just recomputed; restart the direction (beta = 0)
-  S_XALPHA,     // step not yet applied to x: x += S_XALPHA * p (done by the next matvec)
+  S_QZ,         // q.z_new (Polak-Ribiere form of beta)
+  S_REPLACED,   // 1: r was replaced by f - K x this iteration (beta falls back to r.z ratios)
   S_NSLOT
 };
 
@@ -90,19 +108,20 @@ template <typename T> struct Op0Launch {
 
 template <typename T>
 void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal);
-// p_new = z + beta p_old, q = K p_new, partial p.q; also x += alpha_x p_old
-// (the pending iterate update) at owned vertices.
-template <typename T>
-void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q, double* x,
+// p_new = z + beta p_old, q = K p_new, partial p.q (arithmetic in T; z and p
+// stored as V, q as T).
+template <typename T, typename V>
+void op0_matvec_p(const Op0Launch<T>& L, const V* z, const V* pold, V* pnew, T* q,
                   const double* scal, Partials part, int* nblk_out);
-// z0 = Dinv (r - m) (also written out) and t = (r - m) - K z0; m from scal S_MEAN*.
-template <typename T>
-void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
-                  const double* scal);
-// zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW.
-template <typename T>
+// t = (r - m) - K z0; m from scal S_MEAN* (z0 = Dinv (r - m) comes from
+// vec_jacobi0); t is stored as V (it is only restricted, never multiplied by K).
+template <typename T, typename V>
+void op0_residual(const Op0Launch<T>& L, const T* r, const T* z0, V* t, const double* scal);
+// zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW and, if
+// q is given, q.zout in S_QZ.
+template <typename T, typename V>
 void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
-                     const double* scal, Partials part, int* nblk_out);
+                     const T* q, const double* scal, Partials part, int* nblk_out);
 // r = f - K x evaluated in FP64 (x, s and the constants in double), stored as R.
 template <typename R>
 void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
@@ -124,28 +143,31 @@ template <typename T>
 void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipStream_t stm);
 
 // ---------------------------------------------------------------- vectors
-// r -= alpha q; partials ||r||^2 (S_RR) and sum r (S_MEAN*).  The iterate
-// update is deferred (slot S_XALPHA); vec_flush_x applies it: x += alpha_x p.
-template <typename T>
-void vec_update_r(const Grid& g, T* r, const T* q, const double* scal, Partials part,
-                  int* nblk_out, hipStream_t st);
-template <typename T>
-void vec_flush_x(const Grid& g, double* x, const T* p, double* scal, hipStream_t st);
+// x += alpha p (FP64 iterate), r -= alpha q; partials ||r||^2 (S_RR) and
+// sum r (S_MEAN*).
+template <typename T, typename V>
+void vec_update_r(const Grid& g, double* x, const V* p, T* r, const T* q, const double* scal,
+                  Partials part, int* nblk_out, hipStream_t st);
 template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);
 // z = Dinv (r - m) with m from `mean` slots S_MEAN* (NULL: no shift).
-template <typename T>
-void vec_jacobi0(const Grid& g, const T* r, const T* dinv, T* z, const double* scal,
+template <typename R, typename D, typename Z>
+void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,
                  const double* mean, hipStream_t st);
 template <typename T>
 void vec_fill(T* a, int64_t count, T v, hipStream_t st);
+template <typename T>
+void vec_scale(T* a, int64_t count, double factor, hipStream_t st);
+// out[V] = mean of in over the f^3 fine cells of coarse cell V (gf.nx/f cells per axis).
+template <typename T>
+void vec_box_mean(const Grid& gf, const T* in, int f, float* out, hipStream_t st);
 // Deterministic pseudo-random values in [-1, 1) (power-iteration start vectors).
 template <typename T>
 void vec_pattern(T* a, int64_t count, hipStream_t st);
 template <typename T>
 void vec_copy(T* dst, const T* src, int64_t count, hipStream_t st);
-template <typename T>
-void vec_dot_cases(const Grid& g, const T* a, const T* b, const double* scal, Partials part,
+template <typename A, typename B>
+void vec_dot_cases(const Grid& g, const A* a, const B* b, const double* scal, Partials part,
                    int slot, int* nblk_out, hipStream_t st);
 template <typename T>
 void vec_mean_partial(const Grid& g, const T* a, Partials part, int* nblk_out, hipStream_t st);
@@ -161,27 +183,33 @@ void fin_sum(const Partials& part, int slot, int nblk, double* scal, bool all_ca
              hipStream_t st);
 void fin_init(double* scal, double eps_abs, double tol, hipStream_t st);
 void fin_alpha(double* scal, hipStream_t st);
-void fin_beta(double* scal, hipStream_t st);
+// beta = r.z_new / r.z (Fletcher-Reeves), or with polak_ribiere the form
+// -alpha q.z_new / r.z, which tolerates a preconditioner that varies from one
+// application to the next (rounded storage); 0 after a restart.
+void fin_beta(double* scal, bool polak_ribiere, hipStream_t st);
 void fin_mean(const Partials& part, int nblk, int64_t n, double* scal, hipStream_t st);
 void scal_set_all_active(double* scal, hipStream_t st);
 
 // ---------------------------------------------------------------- coarse levels
-template <typename T>
-void kc_apply(const Grid& g, const T* st, const T* u, T* y, hipStream_t s);
-template <typename T>
-void kc_residual(const Grid& g, const T* st, const T* z, const T* r, T* t, const double* scal,
+// T is the storage type of the vectors, W that of the stencils and block
+// inverses; arithmetic runs in Acc<T>.
+template <typename T, typename W>
+void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s);
+template <typename T, typename W>
+void kc_residual(const Grid& g, const W* st, const T* z, const T* r, T* t, const double* scal,
                  const double* mean, hipStream_t s);
-template <typename T>
-void kc_smooth(const Grid& g, const T* st, const T* z, const T* r, const T* dinv, T* zout,
+template <typename T, typename W>
+void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv, T* zout,
                const double* scal, const double* mean, hipStream_t s);
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s);
-template <typename T>
-void prolong_add(const Grid& gf, const Grid& gc, T* zf, const T* ec, const double* scal,
+// zf (fine, type F) (+)= P ec (coarse, type C).
+template <typename F, typename C>
+void prolong_add(const Grid& gf, const Grid& gc, F* zf, const C* ec, const double* scal,
                  bool overwrite, hipStream_t s);
-template <typename T>
-void galerkin_first(const Grid& gf, const Grid& gc, const T* s, const double* msig_dev, T* st,
+template <typename S, typename T>
+void galerkin_first(const Grid& gf, const Grid& gc, const S* s, const double* msig_dev, T* st,
                     hipStream_t stm);
 template <typename T>
 void galerkin_next(const Grid& gf, const Grid& gc, const T* stf, T* stc, hipStream_t stm);
@@ -190,8 +218,8 @@ void dinv_from_stencil(const Grid& g, const T* st, double omega, T* dinv, hipStr
 template <typename T>
 void dense_from_stencil(const Grid& g, const T* st, double* A, hipStream_t stm);
 void gauss_jordan_inverse(int N, double* A, hipStream_t stm);
-template <typename T>
-void coarse_solve(const Grid& g, const double* Ainv, const T* r, T* z, const double* scal,
+template <typename R, typename T>
+void coarse_solve(const Grid& g, const double* Ainv, const R* r, T* z, const double* scal,
                   hipStream_t stm);
 
 // ---------------------------------------------------------------- post-processing

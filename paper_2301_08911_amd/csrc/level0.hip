@@ -10,8 +10,11 @@
 // vertex plane (tile plus a one-vertex halo) is staged in LDS; each thread owns
 // one element column, forms the x/y butterflies from LDS and the z butterfly
 // in registers against the previous plane, and keeps the z-half of its output
-// that belongs to the next vertex plane in registers.  The other half goes
-// through LDS so that each vertex gathers the four element columns around it.
+// that belongs to the next vertex plane in registers.  Lanes run along x, so
+// the x-neighbour part of the vertex gather is a cross-lane move (DPP); only
+// the y-neighbour part goes through LDS.
+#include <type_traits>
+
 #include "hmg_internal.hpp"
 
 namespace hmg {
@@ -45,6 +48,54 @@ TileGeom tile_geom(const Grid& g) {
   t.nzc = (g.nz + lz - 1) / lz;
   t.ntiles = t.ntx * t.nty * t.nzc;
   return t;
+}
+
+// Vertex `xy` of the plane that starts at base + off.  `base + off` is the same
+// for the whole workgroup, so it goes into a buffer resource (scalar registers)
+// and only the 32-bit byte offset of `xy` is per thread (nx*ny*8 < 2^31 is
+// checked on the host).  The range field also turns any offset past 2^31
+// bytes into a dropped access instead of a stray one.
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+
+template <typename P>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const P* base, int64_t off) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(base + off), (short)0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float ld(const float* base, int64_t off, uint32_t xy) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(base, off), xy * 4u, 0, 0));
+}
+__device__ __forceinline__ double ld(const double* base, int64_t off, uint32_t xy) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(base, off), xy * 8u, 0, 0));
+}
+__device__ __forceinline__ bf16 ld(const bf16* base, int64_t off, uint32_t xy) {
+  return __builtin_bit_cast(
+      bf16, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(plane_rsrc(base, off), xy * 2u, 0, 0));
+}
+__device__ __forceinline__ void st(bf16* base, int64_t off, uint32_t xy, bf16 v) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v),
+                                        plane_rsrc(base, off), xy * 2u, 0, 0);
+}
+__device__ __forceinline__ void st(float* base, int64_t off, uint32_t xy, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), plane_rsrc(base, off),
+                                        xy * 4u, 0, 0);
+}
+__device__ __forceinline__ void st(double* base, int64_t off, uint32_t xy, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), plane_rsrc(base, off),
+                                        xy * 8u, 0, 0);
+}
+
+// Value of lane (l - 1) of the wavefront (DPP wave_shr:1); lane 0 receives 0.
+__device__ __forceinline__ float from_left(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 // o[m0 + 2 m1] = sum_{b0,b1} (-1)^(m0 b0 + m1 b1) u[b0 + 2 b1]; self-inverse up to 4.
@@ -128,17 +179,34 @@ __device__ __forceinline__ int logical_block() {
   return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
 }
 
+template <int V>
+using Par = std::integral_constant<int, V>;
+
+// Occupancy target of the level-0 kernels (waves per SIMD), which bounds their
+// register budget: 512 / waves VGPRs.
+#ifndef HMG_OP0_WAVES
+#define HMG_OP0_WAVES 4
+#endif
+template <typename T>
+struct Op0Waves {
+  static constexpr int value = sizeof(T) == 4 ? HMG_OP0_WAVES : 2;
+};
+
 template <typename T, class Op>
-__global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk,
-                                                   const T* __restrict__ s) {
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
+op0_kernel(Op op_in, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) {
   __shared__ T plane[2][3][PY][PX];
-  __shared__ T contrib[2][4][3][TYE][TXE];
+  __shared__ T rowc[2][3][TYE][TXE];
   __shared__ double red[NTHR / 64];
 
   const int j = logical_block();
   const int c = j % NCASE;
   const int tile = j / NCASE;
-  if (!op.active(c)) return;
+  if (!op_in.active(c)) return;
+  // Per-case scalars are read once, before any store of the kernel could be
+  // taken to alias them.
+  Op op = op_in;
+  op.prep(c);
   const int tx = tile % tg.ntx;
   const int rem = tile / tg.ntx;
   const int ty = rem % tg.nty;
@@ -151,7 +219,7 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
 
   // Plane-load slots of this thread (same vertices of every plane); each slot
   // produces the three components of one vertex.
-  int64_t ld_xy[NSLOT];
+  uint32_t ld_xy[NSLOT];
   int ld_pos[NSLOT], ld_gx[NSLOT], ld_gy[NSLOT];
   bool ld_own[NSLOT], ld_ok[NSLOT];
 #pragma unroll
@@ -163,29 +231,27 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
     const int ux = x0 - 1 + px, uy = y0 - 1 + py;
     ld_gx[sl] = modp(ux, g.nx);
     ld_gy[sl] = modp(uy, g.ny);
-    ld_xy[sl] = ld_gx[sl] + (int64_t)g.nx * ld_gy[sl];
+    ld_xy[sl] = (uint32_t)ld_gx[sl] + (uint32_t)g.nx * (uint32_t)ld_gy[sl];
     ld_pos[sl] = ii;
     ld_own[sl] = px >= 1 && px <= OX && py >= 1 && py <= OY && ux < g.nx && uy < g.ny;
   }
   const int ex = modp(x0 - 1 + lx, g.nx), ey = modp(y0 - 1 + ly, g.ny);
-  const int64_t exy = ex + (int64_t)g.nx * ey;
+  const uint32_t exy = (uint32_t)ex + (uint32_t)g.nx * (uint32_t)ey;
   const bool outv = lx >= 1 && ly >= 1 && (x0 - 1 + lx) < g.nx && (y0 - 1 + ly) < g.ny;
 
-  // Global loads of one plane are issued a plane ahead into raw registers
-  // (fetch); the op's arithmetic and its owned-vertex side writes run when the
-  // plane is staged into LDS (stage), so the loads overlap a plane of compute.
-  typename Op::Raw raw[NSLOT];
-  int fetched_z = 0;
-  auto fetch_plane = [&](int zu) {
+  // Global loads of a plane are issued two planes ahead into one of two raw
+  // register sets (fetch); the op's arithmetic and its owned-vertex side writes
+  // run when the plane is staged into LDS (stage), so the loads of two planes
+  // are in flight behind the compute of one.
+  typename Op::Raw raw0[NSLOT], raw1[NSLOT];
+  auto fetch_plane = [&](int zu, typename Op::Raw(&raw)[NSLOT]) {
     const int64_t zoff = nxy * modp(zu, g.nz);
     const bool ownz = zu >= z0 && zu < z1;
-    fetched_z = zu;
 #pragma unroll
     for (int sl = 0; sl < NSLOT; ++sl)
-      if (ld_ok[sl]) op.fetch(c, zoff + ld_xy[sl], ld_own[sl] && ownz, raw[sl]);
+      if (ld_ok[sl]) op.fetch(c, zoff, ld_xy[sl], ld_own[sl] && ownz, raw[sl]);
   };
-  auto stage_plane = [&](int buf) {
-    const int zu = fetched_z;
+  auto stage_plane = [&](int buf, int zu, const typename Op::Raw(&raw)[NSLOT]) {
     const int gz = modp(zu, g.nz);
     const bool ownz = zu >= z0 && zu < z1;
     const int64_t zoff = nxy * gz;
@@ -194,7 +260,7 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
     for (int sl = 0; sl < NSLOT; ++sl)
       if (ld_ok[sl]) {
         T v[3];
-        op.finish(c, zoff + ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz, raw[sl], v);
+        op.finish(c, zoff, ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz, raw[sl], v);
 #pragma unroll
         for (int k = 0; k < 3; ++k) base[k * NVTX + ld_pos[sl]] = v[k];
       }
@@ -209,59 +275,70 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
     }
   };
 
-  // One barrier per plane.  Iteration ez: (A) write the vertex-plane ez-1
-  // contributions computed in the previous iteration and stage vertex plane
-  // ez+1 (prefetched a plane earlier); barrier; (B) gather plane ez-1 and run
-  // its epilogue, then compute element plane ez.  LDS planes and contribution
-  // buffers alternate between iterations.
+  // One barrier per plane.  Step ez: (A) stage vertex plane ez+1 (fetched two
+  // steps earlier); issue the loads of this step; barrier; (B) finish the
+  // gather of vertex plane ez-1 and run its epilogue, then compute element
+  // plane ez.  Element plane ez's output for vertex plane ez is reduced along x
+  // across lanes; the half owed to the vertex row above goes to LDS (read after
+  // the next barrier), the rest stays in registers.  LDS buffers alternate
+  // between steps, and the loop is unrolled twice so that the register sets of
+  // the previous and the new plane alternate instead of being copied.
+  //
+  // Loads retire in issue order as far as the wait counters go, so the loads
+  // of a step are issued by distance to their use: the epilogue operands of
+  // vertex plane ez and the scale of element plane ez+1 (used next step)
+  // first, then vertex plane ez+3 (staged two steps later).  Every load is
+  // unconditional (planes past the chunk wrap around and go unused): a loaded
+  // register merged across a branch would make the compiler wait for all
+  // outstanding loads.
   double acc0 = 0.0, acc1 = 0.0;
-  T tp[4][3], ga[4][3], yq[4][3], ucur[3], uprev[3];
-  fetch_plane(z0 - 1);
-  stage_plane(0);
-  fetch_plane(z0);
+  T ta[4][3], tb[4][3], ga[4][3], rq[3], ucur[3], uprev[3];
+  typename Op::ERaw ea, eb;
+  T sa, sb;
+  // Vertex plane zu lives in raw set (zu - z0 + 1) & 1.  The issue order of
+  // the prologue is pinned so that the loop is entered with the loads in
+  // flight in the order a full step leaves them.
+  fetch_plane(z0 - 1, raw0);
+  __builtin_amdgcn_sched_barrier(0);
+  fetch_plane(z0, raw1);
+  __builtin_amdgcn_sched_barrier(0);
+  stage_plane(0, z0 - 1, raw0);
+  __builtin_amdgcn_sched_barrier(0);
+  sb = ld(s, nxy * modp(z0 - 1, g.nz), exy);
+  __builtin_amdgcn_sched_barrier(0);
+  fetch_plane(z0 + 1, raw0);
+  __builtin_amdgcn_sched_barrier(0);
   lds_barrier();
-  plane_modes(0, tp, ucur);
+  plane_modes(0, ta, ucur);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ga[q][k] = yq[q][k] = T(0);
-  uprev[0] = uprev[1] = uprev[2] = T(0);
-  bool have_y = false;
-  // Per-thread operands of the epilogue (own vertex) and the element scale are
-  // also loaded one plane ahead.
-  typename Op::ERaw eraw;
-  T s_next = s[nxy * modp(z0 - 1, g.nz) + exy];
-  for (int ez = z0 - 1; ez <= z1; ++ez) {
-    const int it = ez - z0 + 1;  // 0, 1, 2, ...
-    const int cb = it & 1;       // contribution buffer of this iteration
-    const int pb = (it + 1) & 1; // plane buffer receiving vertex plane ez + 1
-    if (have_y) {
+    for (int k = 0; k < 3; ++k) ga[q][k] = T(0);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) contrib[cb][b][k][ly][lx] = yq[b][k];
-    }
-    if (ez < z1) {
-      stage_plane(pb);
-      if (ez + 2 <= z1) fetch_plane(ez + 2);
-    }
+  for (int k = 0; k < 3; ++k) rq[k] = uprev[k] = T(0);
+
+  auto step = [&](int ez, auto par, T (&tp)[4][3], T (&tn)[4][3],
+                  typename Op::Raw(&rawn)[NSLOT], typename Op::ERaw& e_new,
+                  const typename Op::ERaw& e_old, T& s_new, const T& s_old) {
+    constexpr int cb = decltype(par)::value;  // row buffer read in this step
+    constexpr int pb = 1 - cb;                // plane buffer receiving vertex plane ez + 1
+    if (ez < z1) stage_plane(pb, ez + 1, rawn);
+    op.efetch(c, nxy * modp(ez, g.nz), exy, e_new);  // epilogue of vertex plane ez
+    s_new = ld(s, nxy * modp(ez + 1, g.nz), exy);     // scale of element plane ez+1
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_plane(ez + 3, rawn);
+    __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
-    if (have_y && outv) {
+    if (ez > z0 && ez <= z1 && outv) {
       T ku[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        ku[k] = (contrib[cb][0][k][ly][lx] + contrib[cb][1][k][ly][lx - 1]) +
-                (contrib[cb][2][k][ly - 1][lx] + contrib[cb][3][k][ly - 1][lx - 1]);
-      op.store(c, nxy * (ez - 1) + exy, ex, ey, ez - 1, ku, uprev, eraw, acc0, acc1);
+      for (int k = 0; k < 3; ++k) ku[k] = rq[k] + rowc[cb][k][ly - 1][lx];
+      op.store(c, nxy * (ez - 1), exy, ex, ey, ez - 1, ku, uprev, e_old, acc0, acc1);
     }
-    // epilogue operands of vertex plane ez (used next iteration)
-    if (outv && ez >= z0 && ez < z1) op.efetch(c, nxy * ez + exy, eraw);
-    have_y = false;
+    const T se = s_old;
     if (ez < z1) {
-      T tn[4][3], unext[3];
+      T unext[3];
       plane_modes(pb, tn, unext);
-      const T se = s_next;
-      if (ez + 1 < z1) s_next = s[nxy * modp(ez + 1, g.nz) + exy];
       T uh[8][3], wh[8][3];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -276,23 +353,30 @@ __global__ void __launch_bounds__(NTHR) op0_kernel(Op op, Grid g, TileGeom tg, M
         for (int k = 0; k < 3; ++k) {
           const T g0 = ga[0][k] + (wh[0][k] + wh[4][k]), g1 = ga[1][k] + (wh[1][k] + wh[5][k]);
           const T g2 = ga[2][k] + (wh[2][k] + wh[6][k]), g3 = ga[3][k] + (wh[3][k] + wh[7][k]);
-          bfly4(g0, g1, g2, g3, yq[0][k], yq[1][k], yq[2][k], yq[3][k]);
+          T y0, y1, y2, y3;
+          bfly4(g0, g1, g2, g3, y0, y1, y2, y3);
+          // corners: 0 -> vertex (lx, ly), 1 -> (lx+1, ly), 2 -> (lx, ly+1), 3 -> (lx+1, ly+1)
+          rq[k] = y0 + from_left(y1);
+          rowc[pb][k][ly][lx] = y2 + from_left(y3);
         }
-        have_y = true;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          ga[q][k] = wh[q][k] - wh[q + 4][k];
-          tp[q][k] = tn[q][k];
-        }
+        for (int k = 0; k < 3; ++k) ga[q][k] = wh[q][k] - wh[q + 4][k];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         uprev[k] = ucur[k];
         ucur[k] = unext[k];
       }
     }
+  };
+  for (int ez = z0 - 1; ez <= z1; ez += 2) {
+    // Steps come in pairs; a step past z1 only issues unused loads and waits
+    // at the barrier.  (An early exit between the two would give the compiler
+    // a path into the loop head with the newest loads still in flight.)
+    step(ez, Par<0>{}, ta, tb, raw1, ea, eb, sa, sb);
+    step(ez + 1, Par<1>{}, tb, ta, raw0, eb, ea, sb, sa);
   }
   if (Op::NACC > 0) {
     const double t0 = block_sum<NTHR / 64>(acc0, red);
@@ -310,9 +394,12 @@ __device__ __forceinline__ bool scal_active(const double* scal, int c) {
 }
 
 // ------------------------------------------------------------------ ops
+// Interface: fetch/finish see vertex `xy` of the plane at offset `zoff`
+// (uniform), efetch/store the thread's own vertex; `c` is the load case.
 template <typename T>
 struct OpApply {
   static constexpr int NACC = 0;
+  __device__ void prep(int) {}
   const T* in;
   T* out;
   int64_t n;
@@ -324,174 +411,170 @@ struct OpApply {
     T u[3];
   };
   struct ERaw {};
-  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+  __device__ void fetch(int c, int64_t zoff, uint32_t xy, bool, Raw& w) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) w.u[k] = in[(int64_t)(c * 3 + k) * n + i];
+    for (int k = 0; k < 3; ++k) w.u[k] = ld(in, (c * 3 + k) * n + zoff, xy);
   }
-  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+  __device__ void finish(int, int64_t, uint32_t, int, int, int, bool, const Raw& w,
+                         T (&v)[3]) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = w.u[k];
   }
-  __device__ void efetch(int, int64_t, ERaw&) const {}
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, const ERaw&,
-                        double&, double&) const {
+  __device__ void efetch(int, int64_t, uint32_t, ERaw&) const {}
+  __device__ void store(int c, int64_t zoff, uint32_t xy, int, int, int, const T* ku, const T*,
+                        const ERaw&, double&, double&) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = ku[k];
+    for (int k = 0; k < 3; ++k) st(out, (c * 3 + k) * n + zoff, xy, ku[k]);
   }
 };
 
 // p_new = z + beta p_old (written at owned vertices), q = K p_new, acc p.q.
-// The iterate update of the previous iteration, x += alpha_x p_old (FP64), is
-// applied at owned vertices on the way (alpha_x from slot S_XALPHA).
-template <typename T>
+// With p stored in a narrower type V, p_new is rounded to V before K is
+// applied, so q = K p holds for the stored direction; q itself stays in T
+// (r -= alpha q must track f - K x to the working precision).
+template <typename T, typename V>
 struct OpMatvecP {
   static constexpr int NACC = 1;
-  const T* z;
-  const T* pold;
-  T* pnew;
+  const V* z;
+  const V* pold;
+  V* pnew;
   T* q;
-  double* x;
   int64_t n;
   const double* scal;
   Partials part;
   int slot0, slot1;
+  T beta;  // set by prep
+  __device__ void prep(int c) { beta = (T)scal[S_BETA * 8 + c]; }
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
   struct Raw {
-    T z[3], p[3];
-    double x[3];
+    V z[3], p[3];
   };
   struct ERaw {};
-  __device__ void fetch(int c, int64_t i, bool own, Raw& w) const {
-    const bool upd = own && scal[S_XALPHA * 8 + c] != 0.0;
+  __device__ void fetch(int c, int64_t zoff, uint32_t xy, bool, Raw& w) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int64_t o = (int64_t)(c * 3 + k) * n + i;
-      w.z[k] = z[o];
-      w.p[k] = pold[o];
-      w.x[k] = upd ? x[o] : 0.0;
+      const int64_t o = (c * 3 + k) * n + zoff;
+      w.z[k] = ld(z, o, xy);
+      w.p[k] = ld(pold, o, xy);
     }
   }
-  __device__ void finish(int c, int64_t i, int, int, int, bool own, const Raw& w,
+  __device__ void finish(int c, int64_t zoff, uint32_t xy, int, int, int, bool own, const Raw& w,
                          T (&v)[3]) const {
-    const T beta = (T)scal[S_BETA * 8 + c];
-    const double ax = scal[S_XALPHA * 8 + c];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int64_t o = (int64_t)(c * 3 + k) * n + i;
-      v[k] = w.z[k] + beta * w.p[k];
-      if (own) {
-        pnew[o] = v[k];
-        if (ax != 0.0) x[o] = w.x[k] + ax * (double)w.p[k];
-      }
+      const V pv = (V)((T)w.z[k] + beta * (T)w.p[k]);
+      v[k] = (T)pv;
+      if (own) st(pnew, (c * 3 + k) * n + zoff, xy, pv);
     }
   }
-  __device__ void efetch(int, int64_t, ERaw&) const {}
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin, const ERaw&,
-                        double& a0, double&) const {
+  __device__ void efetch(int, int64_t, uint32_t, ERaw&) const {}
+  __device__ void store(int c, int64_t zoff, uint32_t xy, int, int, int, const T* ku,
+                        const T* uin, const ERaw&, double& a0, double&) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      q[(int64_t)(c * 3 + k) * n + i] = ku[k];
+      st(q, (c * 3 + k) * n + zoff, xy, ku[k]);
       a0 += (double)uin[k] * (double)ku[k];
     }
   }
 };
 
-// Pre-smoothing from zero and residual: z0 = Dinv (r - m) (formed while the
-// plane is staged, written at owned vertices), t = (r - m) - K z0.  m is the
-// per-component mean of r (FP64), removed before Dinv so that rounding-level
-// translation components of r are not amplified in soft regions.
-template <typename T>
+// Residual after the pre-smoothing from zero: t = (r - m) - K z0, where
+// z0 = Dinv (r - m) was formed pointwise beforehand.  m is the per-component
+// mean of r (FP64), removed so that rounding-level translation components of r
+// are not amplified in soft regions.
+template <typename T, typename V>
 struct OpResidual {
   static constexpr int NACC = 0;
   const T* r;
-  const T* dinv;
-  T* z0;
-  T* t;
+  const T* z0;
+  V* t;
   int64_t n;
   const double* scal;
   Partials part;
   int slot0, slot1;
-  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
-  struct Raw {
-    T r[3], d[6];
-  };
-  struct ERaw {
-    T r[3];
-  };
-  __device__ void efetch(int c, int64_t i, ERaw& e) const {
+  double m[3];  // per-case means of r (set by prep)
+  __device__ void prep(int c) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) e.r[k] = r[(int64_t)(c * 3 + k) * n + i];
+    for (int k = 0; k < 3; ++k) m[k] = scal[(S_MEAN0 + k) * 8 + c];
   }
-  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) w.r[k] = r[(int64_t)(c * 3 + k) * n + i];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) w.d[t] = dinv[(int64_t)t * n + i];
-  }
-  __device__ void finish(int c, int64_t i, int, int, int, bool own, const Raw& w,
-                         T (&v)[3]) const {
-    const T r0 = (T)((double)w.r[0] - scal[S_MEAN0 * 8 + c]);
-    const T r1 = (T)((double)w.r[1] - scal[S_MEAN1 * 8 + c]);
-    const T r2 = (T)((double)w.r[2] - scal[S_MEAN2 * 8 + c]);
-    // dinv planes: xx, yy, zz, xy, yz, xz
-    const T dxx = w.d[0], dyy = w.d[1], dzz = w.d[2], dxy = w.d[3], dyz = w.d[4], dxz = w.d[5];
-    v[0] = dxx * r0 + dxy * r1 + dxz * r2;
-    v[1] = dxy * r0 + dyy * r1 + dyz * r2;
-    v[2] = dxz * r0 + dyz * r1 + dzz * r2;
-    if (own)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) z0[(int64_t)(c * 3 + k) * n + i] = v[k];
-  }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T*, const ERaw& e,
-                        double&, double&) const {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int64_t o = (int64_t)(c * 3 + k) * n + i;
-      t[o] = (T)((double)e.r[k] - scal[(S_MEAN0 + k) * 8 + c]) - ku[k];
-    }
-  }
-};
-
-// Post-smoothing: zout = z1 + D^-1 ((r - m) - K z1), acc (r - m).zout.  z1 is
-// the pre-smoothed correction plus the prolongated coarse correction.
-template <typename T>
-struct OpPostSmooth {
-  static constexpr int NACC = 1;
-  const T* z1;
-  const T* r;
-  const T* dinv;
-  T* zout;
-  int64_t n;
-  const double* scal;
-  Partials part;
-  int slot0, slot1;
   __device__ bool active(int c) const { return scal_active<T>(scal, c); }
   struct Raw {
     T u[3];
   };
   struct ERaw {
-    T r[3], d[6];
+    T r[3];
   };
-  __device__ void efetch(int c, int64_t i, ERaw& e) const {
+  __device__ void efetch(int c, int64_t zoff, uint32_t xy, ERaw& e) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) e.r[k] = r[(int64_t)(c * 3 + k) * n + i];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) e.d[t] = dinv[(int64_t)t * n + i];
+    for (int k = 0; k < 3; ++k) e.r[k] = ld(r, (c * 3 + k) * n + zoff, xy);
   }
-  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+  __device__ void fetch(int c, int64_t zoff, uint32_t xy, bool, Raw& w) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) w.u[k] = z1[(int64_t)(c * 3 + k) * n + i];
+    for (int k = 0; k < 3; ++k) w.u[k] = ld(z0, (c * 3 + k) * n + zoff, xy);
   }
-  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+  __device__ void finish(int, int64_t, uint32_t, int, int, int, bool, const Raw& w,
+                         T (&v)[3]) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) v[k] = w.u[k];
+    for (int k = 0; k < 3; ++k) v[k] = (T)w.u[k];
   }
-  __device__ void store(int c, int64_t i, int, int, int, const T* ku, const T* uin,
-                        const ERaw& e, double& a0, double&) const {
+  __device__ void store(int c, int64_t zoff, uint32_t xy, int, int, int, const T* ku, const T*,
+                        const ERaw& e, double&, double&) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      st(t, (c * 3 + k) * n + zoff, xy, (V)((T)((double)e.r[k] - m[k]) - ku[k]));
+  }
+};
+
+// Post-smoothing: zout = z1 + D^-1 ((r - m) - K z1), acc (r - m).zout.  z1 is
+// the pre-smoothed correction plus the prolongated coarse correction; both it
+// and zout are multiplied by K, so they keep the arithmetic type.
+template <typename T, typename V>
+struct OpPostSmooth {
+  static constexpr int NACC = 2;
+  const T* z1;
+  const T* r;
+  const T* dinv;
+  T* zout;
+  const T* q;  // optional: q of the last matvec, for q.zout
+  int64_t n;
+  const double* scal;
+  Partials part;
+  int slot0, slot1;
+  double m[3];  // per-case means of r (set by prep)
+  __device__ void prep(int c) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[k] = scal[(S_MEAN0 + k) * 8 + c];
+  }
+  __device__ bool active(int c) const { return scal_active<T>(scal, c); }
+  struct Raw {
+    T u[3];
+  };
+  struct ERaw {
+    T r[3], d[6], q[3];
+  };
+  __device__ void efetch(int c, int64_t zoff, uint32_t xy, ERaw& e) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.r[k] = ld(r, (c * 3 + k) * n + zoff, xy);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) e.d[t] = ld(dinv, t * n + zoff, xy);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e.q[k] = q ? ld(q, (c * 3 + k) * n + zoff, xy) : T(0);
+  }
+  __device__ void fetch(int c, int64_t zoff, uint32_t xy, bool, Raw& w) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.u[k] = ld(z1, (c * 3 + k) * n + zoff, xy);
+  }
+  __device__ void finish(int, int64_t, uint32_t, int, int, int, bool, const Raw& w,
+                         T (&v)[3]) const {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = (T)w.u[k];
+  }
+  __device__ void store(int c, int64_t zoff, uint32_t xy, int, int, int, const T* ku,
+                        const T* uin, const ERaw& e, double& a0, double& a1) const {
     T res[3], rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      rv[k] = (T)((double)e.r[k] - scal[(S_MEAN0 + k) * 8 + c]);
+      rv[k] = (T)((double)e.r[k] - m[k]);
       res[k] = rv[k] - ku[k];
     }
     const T dxx = e.d[0], dyy = e.d[1], dzz = e.d[2], dxy = e.d[3], dyz = e.d[4], dxz = e.d[5];
@@ -501,8 +584,9 @@ struct OpPostSmooth {
     zn[2] = uin[2] + (dxz * res[0] + dyz * res[1] + dzz * res[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      zout[(int64_t)(c * 3 + k) * n + i] = zn[k];
+      st(zout, (c * 3 + k) * n + zoff, xy, zn[k]);
       a0 += (double)rv[k] * (double)zn[k];
+      a1 += (double)e.q[k] * (double)zn[k];
     }
   }
 };
@@ -529,6 +613,7 @@ __device__ __forceinline__ void forcing_at(const Grid& g, const T* __restrict__ 
 template <typename T, typename R>
 struct OpForceResidual {
   static constexpr int NACC = 2;
+  __device__ void prep(int) {}
   const T* x;
   R* r;
   const T* s;
@@ -543,23 +628,24 @@ struct OpForceResidual {
     T u[3];
   };
   struct ERaw {};
-  __device__ void efetch(int, int64_t, ERaw&) const {}
-  __device__ void fetch(int c, int64_t i, bool, Raw& w) const {
+  __device__ void efetch(int, int64_t, uint32_t, ERaw&) const {}
+  __device__ void fetch(int c, int64_t zoff, uint32_t xy, bool, Raw& w) const {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) w.u[k] = x[(int64_t)(c * 3 + k) * n + i];
+    for (int k = 0; k < 3; ++k) w.u[k] = ld(x, (c * 3 + k) * n + zoff, xy);
   }
-  __device__ void finish(int, int64_t, int, int, int, bool, const Raw& w, T (&v)[3]) const {
+  __device__ void finish(int, int64_t, uint32_t, int, int, int, bool, const Raw& w,
+                         T (&v)[3]) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = w.u[k];
   }
-  __device__ void store(int c, int64_t i, int gx, int gy, int gz, const T* ku, const T*,
-                        const ERaw&, double& a0, double& a1) const {
+  __device__ void store(int c, int64_t zoff, uint32_t xy, int gx, int gy, int gz, const T* ku,
+                        const T*, const ERaw&, double& a0, double& a1) const {
     T f[3];
     forcing_at(g, s, tpl, c, gx, gy, gz, f);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const T rv = f[k] - ku[k];
-      r[(int64_t)(c * 3 + k) * n + i] = (R)rv;
+      st(r, (c * 3 + k) * n + zoff, xy, (R)rv);
       a0 += (double)f[k] * (double)f[k];
       a1 += (double)rv * (double)rv;
     }
@@ -724,27 +810,26 @@ void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal) {
   launch_op0(L, op);
 }
 
-template <typename T>
-void op0_matvec_p(const Op0Launch<T>& L, const T* z, const T* pold, T* pnew, T* q, double* x,
+template <typename T, typename V>
+void op0_matvec_p(const Op0Launch<T>& L, const V* z, const V* pold, V* pnew, T* q,
                   const double* scal, Partials part, int* nblk_out) {
   // The new direction goes to a separate buffer: the kernel reads halo values of
   // pold that neighbouring blocks must not have overwritten yet.
-  OpMatvecP<T> op{z, pold, pnew, q, x, L.g.n, scal, part, S_PQ, 0};
+  OpMatvecP<T, V> op{z, pold, pnew, q, L.g.n, scal, part, S_PQ, 0, T(0)};
   launch_op0(L, op);
   *nblk_out = tile_geom(L.g).ntiles;
 }
 
-template <typename T>
-void op0_residual(const Op0Launch<T>& L, const T* r, const T* dinv, T* z0, T* t,
-                  const double* scal) {
-  OpResidual<T> op{r, dinv, z0, t, L.g.n, scal, Partials{}, 0, 0};
+template <typename T, typename V>
+void op0_residual(const Op0Launch<T>& L, const T* r, const T* z0, V* t, const double* scal) {
+  OpResidual<T, V> op{r, z0, t, L.g.n, scal, Partials{}, 0, 0, {}};
   launch_op0(L, op);
 }
 
-template <typename T>
+template <typename T, typename V>
 void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
-                     const double* scal, Partials part, int* nblk_out) {
-  OpPostSmooth<T> op{z1, r, dinv, zout, L.g.n, scal, part, S_RZNEW, 0};
+                     const T* q, const double* scal, Partials part, int* nblk_out) {
+  OpPostSmooth<T, V> op{z1, r, dinv, zout, q, L.g.n, scal, part, S_RZNEW, S_QZ, {}};
   launch_op0(L, op);
   *nblk_out = tile_geom(L.g).ntiles;
 }
@@ -785,14 +870,14 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
                      s, K0_dev, st);
 }
 
-#define HMG_INST(T)                                                                              \
-  template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
-  template void op0_matvec_p<T>(const Op0Launch<T>&, const T*, const T*, T*, T*, double*,       \
-                                const double*, Partials, int*);                                  \
-  template void op0_residual<T>(const Op0Launch<T>&, const T*, const T*, T*, T*,               \
-                                const double*);                                                  \
-  template void op0_post_smooth<T>(const Op0Launch<T>&, const T*, const T*, const T*, T*,       \
+#define HMG_INST2(T, V)                                                                          \
+  template void op0_matvec_p<T, V>(const Op0Launch<T>&, const V*, const V*, V*, T*,             \
                                    const double*, Partials, int*);                               \
+  template void op0_residual<T, V>(const Op0Launch<T>&, const T*, const T*, V*, const double*); \
+  template void op0_post_smooth<T, V>(const Op0Launch<T>&, const T*, const T*, const T*, T*,    \
+                                      const T*, const double*, Partials, int*);
+#define HMG_INST1(T)                                                                             \
+  template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
   template void op0_force_residual<T>(const Op0Launch<double>&, const LoadTpl<double>&,         \
                                       const double*, T*, const double*, Partials, int*);         \
   template void forcing<T>(const Grid&, const LoadTpl<double>&, const double*, T*, Partials,    \
@@ -801,8 +886,12 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
                               double, double, int*, hipStream_t);                                 \
   template void dinv_level0<T>(const Grid&, const T*, double, double, double, T*, hipStream_t);  \
   template void stencil_level0<T>(const Grid&, const T*, const double*, T*, hipStream_t);
-HMG_INST(float)
-HMG_INST(double)
-#undef HMG_INST
+HMG_INST1(float)
+HMG_INST1(double)
+HMG_INST2(float, float)
+HMG_INST2(double, double)
+HMG_INST2(float, bf16)
+#undef HMG_INST1
+#undef HMG_INST2
 
 }  // namespace hmg

@@ -14,10 +14,13 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hmg.h"
+#include "../../include/hmg_nn.h"
 #include "hmg_internal.hpp"
+#include "nn_internal.hpp"
 
 using namespace hmg;
 
@@ -56,7 +59,7 @@ class DeviceArena {
 // around the tracked launches; elapsed times are harvested when read.
 class KernelClock {
  public:
-  static constexpr int NK = 5;
+  static constexpr int NK = 6;
   ~KernelClock() {
     for (auto& p : pending_) {
       (void)hipEventDestroy(p.a);
@@ -147,6 +150,7 @@ class SolverIface {
   virtual Status loads(void* f) = 0;
   virtual Status vcycle(const void* r, void* z) = 0;
   virtual Status transfer(int level, int dir, const void* in, void* out) = 0;
+  virtual Status warm_start(Net& net, double accept, double* relres, int* used) = 0;
   virtual int levels() const = 0;
   virtual Grid level_grid(int l) const = 0;
   virtual double level_omega(int l) const = 0;
@@ -177,8 +181,15 @@ Status check_hip(const char* where) {
     if (_s.code != HMG_OK) return _s;        \
   } while (0)
 
-template <typename T>
+// T: arithmetic type of the solver vectors; V: their storage type (and that of
+// the coarse stencils).  The FP64 iterate, the FP64 scalars and the level-0
+// residual r (type T) are the same in every form.
+template <typename T, typename V, typename W>
 class Solver final : public SolverIface {
+  // Rounded storage makes the preconditioner vary slightly between
+  // applications; beta then takes the Polak-Ribiere form.
+  static constexpr bool kPR = !std::is_same<T, V>::value;
+
  public:
   Solver(const hmg_config& cfg, hipStream_t st, const ElementConsts& ec, std::vector<Grid> grids)
       : cfg_(cfg), st_(st), ec_(ec), grids_(std::move(grids)) {}
@@ -215,24 +226,30 @@ class Solver final : public SolverIface {
     }
     r_ = (T*)A(sizeof(T) * F);
     z_ = (T*)A(sizeof(T) * F);
-    t_ = (T*)A(sizeof(T) * F);
+    t_ = (V*)A(sizeof(V) * F);
     pa_ = (T*)A(sizeof(T) * F);
     pb_ = (T*)A(sizeof(T) * F);
     q_ = (T*)A(sizeof(T) * F);
+    // The plain forms reuse q (dead while the V-cycle runs); the reduced-
+    // precision form keeps q for the Polak-Ribiere beta.
+    w0_ = kPR ? (T*)A(sizeof(T) * F) : q_;
     const int L = levels();
     lev_.resize(L);
     for (int l = 1; l < L; ++l) {
       const Grid& g = grids_[l];
       const int64_t Fl = (int64_t)NCASE * 3 * g.n;
-      lev_[l].st = (T*)A(sizeof(T) * 243 * g.n);
-      lev_[l].dinv = (T*)A(sizeof(T) * 6 * g.n);
-      lev_[l].r = (T*)A(sizeof(T) * Fl);
-      lev_[l].z = (T*)A(sizeof(T) * Fl);
-      lev_[l].t = (T*)A(sizeof(T) * Fl);
+      lev_[l].st = (W*)A(sizeof(W) * 243 * g.n);
+      lev_[l].dinv = (W*)A(sizeof(W) * 6 * g.n);
+      lev_[l].r = (V*)A(sizeof(V) * Fl);
+      lev_[l].z = (V*)A(sizeof(V) * Fl);
+      lev_[l].t = (V*)A(sizeof(V) * Fl);
       lev_[l].ms = (double*)A(sizeof(double) * S_NSLOT * 8);
     }
     const Grid& gL = grids_[L - 1];
     ncdof_ = (int)(3 * gL.n);
+    // the coarsest correction is the largest, smoothest field of the cycle and
+    // is multiplied by K after prolongation: it keeps the arithmetic type
+    if (L > 1) zc_ = (T*)A(sizeof(T) * NCASE * 3 * gL.n);
     Ainv_ = (double*)A(sizeof(double) * ((size_t)ncdof_ * ncdof_ + ncdof_));
     if (L == 1) st0_ = (T*)A(sizeof(T) * 243 * g0.n);
     stride_ = std::max(op0_blocks_per_case(g0), 4096);
@@ -268,6 +285,75 @@ class Solver final : public SolverIface {
 
   ~Solver() override {
     if (hscal_) (void)hipHostFree(hscal_);
+    if (nnbuf_) (void)hipFree(nnbuf_);
+  }
+
+  // Learned initial guess (see hmg_warm_start): density box mean on level lt,
+  // network prediction of u/N there, times N, zero mean per component,
+  // trilinear prolongation to the fine grid, FP64 residual test.
+  Status warm_start(Net& net, double accept, double* relres, int* used) override {
+    if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
+    const Grid& g0 = grids_[0];
+    if (g0.nx != g0.ny || g0.nx != g0.nz) return fail(HMG_E_INVALID, "warm start needs a cubic cell");
+    if (net.in_channels() != 1 || net.out_channels() != 3 * NCASE)
+      return fail(HMG_E_INVALID, "the network must map 1 channel to %d", 3 * NCASE);
+    int lt = -1;
+    for (int l = 0; l < levels(); ++l) {
+      const int d = grids_[l].nx;
+      if (d <= 64 && d % net.dim_multiple() == 0 && d >= net.min_dim()) {
+        lt = l;
+        break;
+      }
+    }
+    if (lt < 0) return fail(HMG_E_INVALID, "no multigrid level of this cell fits the network");
+    const Grid& gt = grids_[lt];
+    const int64_t Ft = (int64_t)NCASE * 3 * gt.n, F = (int64_t)NCASE * 3 * g0.n;
+    if (!nnbuf_ && hipMalloc((void**)&nnbuf_, sizeof(float) * 19 * 64 * 64 * 64) != hipSuccess)
+      return fail(HMG_E_OOM, "warm-start buffer allocation failed");
+    float* xin = nnbuf_;
+    float* yout = nnbuf_ + gt.n;
+    vec_box_mean<T>(g0, rho_, g0.nx / gt.nx, xin, st_);
+    const std::string e = net.forward(xin, 1, gt.nx, yout);
+    if (!e.empty()) return fail(HMG_E_DEVICE, "%s", e.c_str());
+    vec_scale<float>(yout, Ft, (double)g0.nx, st_);  // u = N * (u / N)
+    int nb = 0;
+    vec_mean_partial<float>(gt, yout, part_, &nb, st_);
+    fin_mean(part_, nb, gt.n, aux_, st_);
+    vec_mean_subtract<float>(gt, yout, aux_, st_);
+    if (lt == 0) {
+      vec_convert<float, double>(x_, yout, F, st_);
+    } else {
+      vec_convert<float, V>(lev_[lt].z, yout, Ft, st_);
+      for (int l = lt - 1; l >= 1; --l)
+        prolong_add<V, V>(grids_[l], grids_[l + 1], lev_[l].z, lev_[l + 1].z, nullptr, true, st_);
+      prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, nullptr, true, st_);
+      vec_convert<T, double>(x_, w0_, F, st_);
+    }
+    Op0Launch<double> L64{g0, mk64_, s64_, st_};
+    scal_set_all_active(aux_, st_);
+    op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
+    fin_sum(part_, S_FF, nb, aux_, true, st_);
+    fin_sum(part_, S_TRUE, nb, aux_, true, st_);
+    HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+    const double* ha = hscal_ + S_NSLOT * 8;
+    const double lam1 = cfg_.nu / ((1 + cfg_.nu) * (1 - 2 * cfg_.nu));
+    const double mu1 = 1.0 / (2 * (1 + cfg_.nu));
+    const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * mean_s_;
+    double worst = 0.0;
+    for (int c = 0; c < NCASE; ++c) {
+      const double ff = std::sqrt(ha[S_FF * 8 + c]), tr = std::sqrt(ha[S_TRUE * 8 + c]);
+      if (ff > eps_abs) worst = std::max(worst, tr / ff);
+    }
+    *relres = worst;
+    *used = worst <= accept ? 1 : 0;
+    if (*used) {
+      have_iterate_ = true;
+    } else {
+      vec_fill<double>(x_, F, 0.0, st_);
+      have_iterate_ = false;
+    }
+    have_solution_ = false;
+    return check_hip("warm_start");
   }
 
   Status set_density(const float* rho) override {
@@ -289,20 +375,23 @@ class Solver final : public SolverIface {
     dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
     for (int l = 1; l < L; ++l) {
       if (l == 1)
-        galerkin_first<T>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
+        galerkin_first<T, W>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
       else
-        galerkin_next<T>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
+        galerkin_next<W>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
       if (l == L - 1) continue;  // the coarsest level is solved directly
-      dinv_from_stencil<T>(grids_[l], lev_[l].st, 1.0, lev_[l].dinv, st_);
+      dinv_from_stencil<W>(grids_[l], lev_[l].st, 1.0, lev_[l].dinv, st_);
       double lam = 0.0;
       HMG_TRY(estimate_lambda(l, &lam));
       lambda_[l] = lam;
       omega_[l] = omega_for(lam);
-      dinv_from_stencil<T>(grids_[l], lev_[l].st, omega_[l], lev_[l].dinv, st_);
+      dinv_from_stencil<W>(grids_[l], lev_[l].st, omega_[l], lev_[l].dinv, st_);
     }
-    const T* stc = (L == 1) ? st0_ : lev_[L - 1].st;
-    if (L == 1) stencil_level0<T>(g0, s_, K0dev_, st0_, st_);
-    dense_from_stencil<T>(grids_[L - 1], stc, Ainv_, st_);
+    if (L == 1) {
+      stencil_level0<T>(g0, s_, K0dev_, st0_, st_);
+      dense_from_stencil<T>(g0, st0_, Ainv_, st_);
+    } else {
+      dense_from_stencil<W>(grids_[L - 1], lev_[L - 1].st, Ainv_, st_);
+    }
     gauss_jordan_inverse(ncdof_, Ainv_, st_);
     double ssum = 0.0;
     (void)hipMemcpyAsync(&ssum, misc_, sizeof(double), hipMemcpyDeviceToHost, st_);
@@ -310,7 +399,7 @@ class Solver final : public SolverIface {
     HMG_TRY(check_hip("set_density"));
     mean_s_ = ssum / (double)g0.n;
     have_density_ = true;
-    have_solution_ = false;
+    have_solution_ = false;  // x_ stays as the start of an init = 1 solve
     return Status{};
   }
 
@@ -320,7 +409,7 @@ class Solver final : public SolverIface {
     if (!(tol > 0.0) || max_iter <= 0 || init < 0 || init > 2 || (init == 2 && !u0))
       return fail(HMG_E_INVALID, "bad solve arguments (tol %g, max_iter %d, init %d)", tol,
                   max_iter, init);
-    if (init == 1 && !have_solution_) init = 0;
+    if (init == 1 && !have_iterate_) init = 0;
     const Grid& g0 = grids_[0];
     const int64_t F = (int64_t)NCASE * 3 * g0.n;
     const int64_t cs = 3 * g0.n;
@@ -363,7 +452,7 @@ class Solver final : public SolverIface {
     T* pnew = pb_;
     active_count_ = count(active);
     if (any(active)) {
-      HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
+      HMG_TRY(vcycle_apply(r_, z_, nullptr, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
       (void)hipMemcpyAsync(scal_ + S_RZ * 8, scal_ + S_RZNEW * 8, sizeof(double) * 8,
                            hipMemcpyDeviceToDevice, st_);
@@ -371,39 +460,42 @@ class Solver final : public SolverIface {
     int it = 0;
     while (any(active) && it < max_iter) {
       ++it;
-      const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T);
-      clock.timed(HMG_K_MATVEC, vn * (nact * (12 * TB + (it > 1 ? 48 : 0)) + TB), st_, [&] {
-        op0_matvec_p<T>(L0, z_, pold, pnew, q_, x_, scal_, part_, &nb);
+      const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T), VB = sizeof(V);
+      clock.timed(HMG_K_MATVEC, vn * (nact * 12 * TB + TB), st_, [&] {
+        op0_matvec_p<T, T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
       });
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      clock.timed(HMG_K_UPDATE, vn * nact * 9 * TB, st_, [&] {
-        vec_update_r<T>(g0, r_, q_, scal_, part_, &nb, st_);
+      clock.timed(HMG_K_UPDATE, vn * nact * (12 * TB + 48), st_, [&] {
+        vec_update_r<T, T>(g0, x_, pnew, r_, q_, scal_, part_, &nb, st_);
       });
       fin_sum(part_, S_RR, nb, scal_, false, st_);
       fin_mean(part_, nb, g0.n, scal_, st_);
       std::swap(pold, pnew);
       for (int c = 0; c < NCASE; ++c) it_count[c] += active[c] ? 1 : 0;
       HMG_TRY(read_scal(scal_, hscal_));
-      bool check[NCASE];
+      bool check[NCASE], event[NCASE];
       bool anycheck = false;
       const bool replace = cfg_.replace_every > 0 && it % cfg_.replace_every == 0;
       for (int c = 0; c < NCASE; ++c) {
         const double rn = std::sqrt(hscal_[S_RR * 8 + c]);
-        // recompute when the recursive residual claims convergence, every
-        // replace_every iterations, or once it has dropped 100x below the last
-        // recomputed one (low-precision recursions drift from f - K x)
-        check[c] = active[c] && (replace || rn <= hscal_[S_THRESH * 8 + c] ||
-                                 rn <= 1e-2 * last_true_[c]);
+        // recompute when the recursive residual claims convergence or has
+        // dropped 100x below the last recomputed one (low-precision
+        // recursions drift from f - K x; the direction restarts then), and
+        // every replace_every iterations (plain residual replacement, the
+        // direction is kept)
+        event[c] = active[c] && (rn <= hscal_[S_THRESH * 8 + c] || rn <= 1e-2 * last_true_[c]);
+        check[c] = event[c] || (active[c] && replace);
         anycheck |= check[c];
       }
       if (anycheck) {
         // Confirm on the residual f - K x recomputed in FP64 before a case
-        // stops; the recomputed residual also replaces the recursive one.
-        vec_flush_x<T>(g0, x_, pold, scal_, st_);  // pold now holds this iteration's p
+        // stops; the recomputed residual also replaces the recursive one (it
+        // is written over r of the checked cases: a case that stops no longer
+        // needs r).
         set_mask(aux_, check);
         clock.timed(HMG_K_TRUE_RESIDUAL, (double)g0.n * (count(check) * (24 + 3 * sizeof(T)) + 8),
-                    st_, [&] { op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb); });
+                    st_, [&] { op0_force_residual<T>(L64, tpl64_, x_, r_, aux_, part_, &nb); });
         fin_sum(part_, S_TRUE, nb, aux_, false, st_);
         HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
         const double* ha = hscal_ + S_NSLOT * 8;
@@ -413,31 +505,29 @@ class Solver final : public SolverIface {
           if (!check[c]) continue;
           const double tr = std::sqrt(ha[S_TRUE * 8 + c]);
           last_true_[c] = tr;
-          if (tr <= hscal_[S_THRESH * 8 + c]) {
+          if (tr <= hscal_[S_THRESH * 8 + c])
             active[c] = false;
-          } else {
-            (void)hipMemcpyAsync(r_ + c * cs, t_ + c * cs, sizeof(T) * cs, hipMemcpyDeviceToDevice,
-                                 st_);
-            restart[c] = true;
-          }
+          else
+            restart[c] = event[c];
         }
         set_mask(scal_, active);
         set_slot(scal_, S_RESTART, restart);
+        set_slot(scal_, S_REPLACED, check);
         residual_mean(scal_);
       }
       if (!any(active)) break;
       active_count_ = count(active);
-      HMG_TRY(vcycle_apply(r_, z_, scal_, &nb));
+      HMG_TRY(vcycle_apply(r_, z_, kPR ? q_ : nullptr, scal_, &nb));
       fin_sum(part_, S_RZNEW, nb, scal_, false, st_);
-      fin_beta(scal_, st_);
+      if (kPR) fin_sum(part_, S_QZ, nb, scal_, false, st_);
+      fin_beta(scal_, kPR, st_);
     }
-    // Pending iterate updates, zero-mean solution, recomputed final residuals.
-    vec_flush_x<T>(g0, x_, pold, scal_, st_);
+    // Zero-mean solution, recomputed final residuals.
     vec_mean_partial<double>(g0, x_, part_, &nb, st_);
     fin_mean(part_, nb, g0.n, aux_, st_);
     vec_mean_subtract<double>(g0, x_, aux_, st_);
     scal_set_all_active(aux_, st_);
-    op0_force_residual<T>(L64, tpl64_, x_, t_, aux_, part_, &nb);
+    op0_force_residual<T>(L64, tpl64_, x_, r_, aux_, part_, &nb);
     fin_sum(part_, S_FF, nb, aux_, true, st_);
     fin_sum(part_, S_TRUE, nb, aux_, true, st_);
     HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
@@ -449,6 +539,7 @@ class Solver final : public SolverIface {
       relres[c] = trivial || ff <= 0.0 ? 0.0 : std::sqrt(ha[S_TRUE * 8 + c] / ff);
     }
     have_solution_ = true;
+    have_iterate_ = true;
     if (any(active))
       return fail(HMG_E_NOT_CONVERGED, "max_iter %d reached before rel_tol %g", max_iter, tol);
     return Status{};
@@ -464,12 +555,13 @@ class Solver final : public SolverIface {
     return check_hip("elastic_tensor");
   }
 
-  Status sens(const double W[36], float* out) override {
+  Status sens(const double Wt[36], float* out) override {
     if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
     double w21[21];
     int t = 0;
     for (int j = 0; j < NCASE; ++j)
-      for (int i = 0; i <= j; ++i) w21[t++] = (i == j) ? W[i * 6 + i] : W[i * 6 + j] + W[j * 6 + i];
+      for (int i = 0; i <= j; ++i)
+        w21[t++] = (i == j) ? Wt[i * 6 + i] : Wt[i * 6 + j] + Wt[j * 6 + i];
     (void)hipMemcpyAsync(misc_ + 36, w21, sizeof(double) * 21, hipMemcpyHostToDevice, st_);
     const double coef = cfg_.penal * (cfg_.E0 - cfg_.Emin) / (double)grids_[0].n;
     sensitivity<double>(grids_[0], mk64_, chh64_, rho64_, x_, misc_ + 36, coef, cfg_.penal, out,
@@ -485,13 +577,18 @@ class Solver final : public SolverIface {
     return check_hip("get_displacement");
   }
 
+  // The inspection entry points below take and return fields of type T; with
+  // a narrower storage type the coarse-level data pass through conversions.
   Status apply_op(int level, const void* u, void* y) override {
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
     if (level == 0) {
       Op0Launch<T> L0{grids_[0], mk_, s_, st_};
       op0_apply<T>(L0, (const T*)u, (T*)y, nullptr);
     } else {
-      kc_apply<T>(grids_[level], lev_[level].st, (const T*)u, (T*)y, st_);
+      const int64_t Fl = (int64_t)NCASE * 3 * grids_[level].n;
+      vec_convert<T, V>(lev_[level].z, (const T*)u, Fl, st_);
+      kc_apply<V, W>(grids_[level], lev_[level].st, lev_[level].z, lev_[level].t, st_);
+      vec_convert<V, T>((T*)y, lev_[level].t, Fl, st_);
     }
     return check_hip("apply_operator");
   }
@@ -501,8 +598,7 @@ class Solver final : public SolverIface {
     if (level == 0)
       stencil_level0<T>(grids_[0], s_, K0dev_, (T*)out, st_);
     else
-      (void)hipMemcpyAsync(out, lev_[level].st, sizeof(T) * 243 * grids_[level].n,
-                     hipMemcpyDeviceToDevice, st_);
+      vec_convert<W, T>((T*)out, lev_[level].st, 243 * grids_[level].n, st_);
     return check_hip("get_stencil");
   }
 
@@ -519,27 +615,32 @@ class Solver final : public SolverIface {
     int nb = 0;
     vec_mean_partial<T>(grids_[0], (const T*)r, part_, &nb, st_);
     fin_mean(part_, nb, grids_[0].n, aux_, st_);
-    HMG_TRY(vcycle_apply((const T*)r, (T*)z, aux_, &nb));
+    HMG_TRY(vcycle_apply((const T*)r, (T*)z, nullptr, aux_, &nb));
     return check_hip("vcycle");
   }
 
   Status transfer(int level, int dir, const void* in, void* out) override {
     const Grid& gf = grids_[level];
     const Grid& gc = grids_[level + 1];
-    if (dir == 0)
-      restrict_to<T>(gf, gc, (const T*)in, (T*)out, nullptr, st_);
-    else
-      prolong_add<T>(gf, gc, (T*)out, (const T*)in, nullptr, true, st_);
+    const int64_t Ff = (int64_t)NCASE * 3 * gf.n, Fc = (int64_t)NCASE * 3 * gc.n;
+    if (dir == 0) {
+      vec_convert<T, V>(t_, (const T*)in, Ff, st_);
+      restrict_to<V>(gf, gc, t_, lev_[level + 1].r, nullptr, st_);
+      vec_convert<V, T>((T*)out, lev_[level + 1].r, Fc, st_);
+    } else {
+      vec_convert<T, V>(lev_[level + 1].z, (const T*)in, Fc, st_);
+      prolong_add<T, V>(gf, gc, (T*)out, lev_[level + 1].z, nullptr, true, st_);
+    }
     return check_hip("transfer");
   }
 
  private:
   struct Lev {
-    T* st = nullptr;
-    T* dinv = nullptr;
-    T* r = nullptr;
-    T* z = nullptr;
-    T* t = nullptr;
+    W* st = nullptr;
+    W* dinv = nullptr;
+    V* r = nullptr;
+    V* z = nullptr;
+    V* t = nullptr;
     double* ms = nullptr;  // FP64 per-component means of r at this level (slots S_MEAN*)
   };
 
@@ -560,17 +661,17 @@ class Solver final : public SolverIface {
     Lev& lv = lev_[l];
     const Grid& g = grids_[l];
     const int64_t F = (int64_t)NCASE * 3 * g.n;
-    vec_pattern<T>(lv.z, F, st_);
+    vec_pattern<V>(lv.z, F, st_);
     for (int k = 0; k < 15; ++k) {
-      kc_apply<T>(g, lv.st, lv.z, lv.t, st_);                        // y = K x
-      vec_jacobi0<T>(g, lv.t, lv.dinv, lv.z, nullptr, nullptr, st_);  // x = D^-1 y
+      kc_apply<V, W>(g, lv.st, lv.z, lv.t, st_);                        // y = K x
+      vec_jacobi0<V, W, V>(g, lv.t, lv.dinv, lv.z, nullptr, nullptr, st_);  // x = D^-1 y
     }
-    kc_apply<T>(g, lv.st, lv.z, lv.r, st_);
+    kc_apply<V, W>(g, lv.st, lv.z, lv.r, st_);
     scal_set_all_active(aux_, st_);
     int nb = 0;
-    vec_dot_cases<T>(g, lv.z, lv.r, aux_, part_, S_PQ, &nb, st_);   // x^T K x
+    vec_dot_cases<V, V>(g, lv.z, lv.r, aux_, part_, S_PQ, &nb, st_);   // x^T K x
     fin_sum(part_, S_PQ, nb, aux_, true, st_);
-    vec_dot_cases<T>(g, lv.z, lv.t, aux_, part_, S_RZ, &nb, st_);   // x^T D x
+    vec_dot_cases<V, V>(g, lv.z, lv.t, aux_, part_, S_RZ, &nb, st_);   // x^T D x
     fin_sum(part_, S_RZ, nb, aux_, true, st_);
     HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
     const double* ha = hscal_ + S_NSLOT * 8;
@@ -619,24 +720,30 @@ class Solver final : public SolverIface {
   // the translation component of every residual removed in FP64 before the
   // block-Jacobi smoother and the coarsest solve.  scal supplies the active
   // cases and the means of r0; per-block partials of (r0 - m).zout are left in
-  // slot S_RZNEW.  Work buffers: q_ (pre-smoothed z0) and t_.
-  Status vcycle_apply(const T* r0, T* zout, const double* scal, int* nb) {
+  // slot S_RZNEW.  Work buffers: w0_ (pre-smoothed z0, aliases q_) and t_.
+  Status vcycle_apply(const T* r0, T* zout, const T* qpr, const double* scal, int* nb) {
     const int L = levels();
     const Grid& g0 = grids_[0];
     if (L == 1) {
-      coarse_solve<T>(g0, Ainv_, r0, zout, scal, st_);
-      vec_dot_cases<T>(g0, r0, zout, scal, part_, S_RZNEW, nb, st_);
+      coarse_solve<T, T>(g0, Ainv_, r0, zout, scal, st_);
+      if (qpr) vec_dot_cases<T, T>(g0, qpr, zout, scal, part_, S_QZ, nb, st_);
+      vec_dot_cases<T, T>(g0, r0, zout, scal, part_, S_RZNEW, nb, st_);
       return check_hip("vcycle");
     }
     Op0Launch<T> L0{g0, mk_, s_, st_};
-    const double vn = (double)g0.n, TB = sizeof(T), nact = active_count_;
-    clock.timed(HMG_K_RESIDUAL, vn * (nact * 9 * TB + 7 * TB), st_,
-                [&] { op0_residual<T>(L0, r0, dinv0_, q_, t_, scal); });
-    restrict_to<T>(g0, grids_[1], t_, lev_[1].r, scal, st_);
+    const double vn = (double)g0.n, TB = sizeof(T), VB = sizeof(V), nact = active_count_;
+    clock.timed(HMG_K_JACOBI, vn * (nact * 6 * TB + 6 * TB), st_,
+                [&] { vec_jacobi0<T, T, T>(g0, r0, dinv0_, w0_, scal, scal, st_); });
+    clock.timed(HMG_K_RESIDUAL, vn * (nact * 3 * (2 * TB + VB) + TB), st_,
+                [&] { op0_residual<T, V>(L0, r0, w0_, t_, scal); });
+    restrict_to<V>(g0, grids_[1], t_, lev_[1].r, scal, st_);
     descend(1, scal);
-    prolong_add<T>(g0, grids_[1], q_, lev_[1].z, scal, false, st_);
-    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 9 * TB + 7 * TB), st_, [&] {
-      op0_post_smooth<T>(L0, q_, r0, dinv0_, zout, scal, part_, nb);
+    if (L == 2)
+      prolong_add<T, T>(g0, grids_[1], w0_, zc_, scal, false, st_);
+    else
+      prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, scal, false, st_);
+    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 3 * (3 * TB + (qpr ? TB : 0)) + 7 * TB), st_, [&] {
+      op0_post_smooth<T, V>(L0, w0_, r0, dinv0_, zout, qpr, scal, part_, nb);
     });
     return check_hip("vcycle");
   }
@@ -646,18 +753,21 @@ class Solver final : public SolverIface {
     Lev& lv = lev_[l];
     const Grid& g = grids_[l];
     if (l == L - 1) {
-      coarse_solve<T>(g, Ainv_, lv.r, lv.z, scal, st_);
+      coarse_solve<V, T>(g, Ainv_, lv.r, zc_, scal, st_);
       return;
     }
     int nb = 0;
-    vec_mean_partial<T>(g, lv.r, part_, &nb, st_);
+    vec_mean_partial<V>(g, lv.r, part_, &nb, st_);
     fin_mean(part_, nb, g.n, lv.ms, st_);
-    vec_jacobi0<T>(g, lv.r, lv.dinv, lv.z, scal, lv.ms, st_);
-    kc_residual<T>(g, lv.st, lv.z, lv.r, lv.t, scal, lv.ms, st_);
-    restrict_to<T>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
+    vec_jacobi0<V, W, V>(g, lv.r, lv.dinv, lv.z, scal, lv.ms, st_);
+    kc_residual<V, W>(g, lv.st, lv.z, lv.r, lv.t, scal, lv.ms, st_);
+    restrict_to<V>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
     descend(l + 1, scal);
-    prolong_add<T>(g, grids_[l + 1], lv.z, lev_[l + 1].z, scal, false, st_);
-    kc_smooth<T>(g, lv.st, lv.z, lv.r, lv.dinv, lv.t, scal, lv.ms, st_);
+    if (l + 1 == L - 1)
+      prolong_add<V, T>(g, grids_[l + 1], lv.z, zc_, scal, false, st_);
+    else
+      prolong_add<V, V>(g, grids_[l + 1], lv.z, lev_[l + 1].z, scal, false, st_);
+    kc_smooth<V, W>(g, lv.st, lv.z, lv.r, lv.dinv, lv.t, scal, lv.ms, st_);
     std::swap(lv.z, lv.t);
   }
 
@@ -675,8 +785,13 @@ class Solver final : public SolverIface {
   double* s64_ = nullptr;    // FP64 copies used by the residual recomputation and C^H
   double* rho64_ = nullptr;
   double* x_ = nullptr;      // iterate kept in FP64
-  T *r_ = nullptr, *z_ = nullptr, *t_ = nullptr;
-  T *pa_ = nullptr, *pb_ = nullptr, *q_ = nullptr;
+  T* r_ = nullptr;  // level-0 residual (arithmetic type)
+  T* z_ = nullptr;  // preconditioned residual
+  V* t_ = nullptr;  // V-cycle work: level-0 residual after pre-smoothing
+  T *pa_ = nullptr, *pb_ = nullptr;
+  T* q_ = nullptr;   // q = K p
+  T* w0_ = nullptr;  // V-cycle level-0 correction (the plain forms alias q_)
+  T* zc_ = nullptr;  // coarsest-level correction
   T* st0_ = nullptr;
   std::vector<Lev> lev_;
   double* Ainv_ = nullptr;
@@ -694,7 +809,9 @@ class Solver final : public SolverIface {
   std::vector<double> lambda_;  // spectral bound of D^-1 K per level
   double last_true_[NCASE] = {};  // last recomputed residual norm per case
   bool have_density_ = false;
-  bool have_solution_ = false;
+  bool have_solution_ = false;  // x_ solves the current density (C^H, sensitivities)
+  bool have_iterate_ = false;   // x_ holds a solution or an accepted guess (init = 1)
+  float* nnbuf_ = nullptr;      // warm start: network input and output (<= 64^3)
 };
 
 }  // namespace
@@ -724,6 +841,8 @@ Status validate(const hmg_config& c, std::vector<Grid>* grids) {
     return fail(HMG_E_INVALID, "every axis needs at least 4 cells (got %dx%dx%d)", c.nx, c.ny, c.nz);
   if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 31)
     return fail(HMG_E_INVALID, "cell too large");
+  if ((int64_t)c.nx * c.ny > (int64_t)1 << 27)
+    return fail(HMG_E_INVALID, "an xy plane may hold at most 2^27 cells (got %dx%d)", c.nx, c.ny);
   if (!(c.E0 > 0.0) || !(c.nu > -1.0 && c.nu < 0.5) || !(c.penal >= 1.0) || !(c.Emin >= 0.0) ||
       !(c.Emin < c.E0))
     return fail(HMG_E_INVALID, "bad material (E0 %g, nu %g, penal %g, Emin %g)", c.E0, c.nu,
@@ -731,7 +850,8 @@ Status validate(const hmg_config& c, std::vector<Grid>* grids) {
   if (c.omega < 0.0 || c.omega >= 1.0) return fail(HMG_E_INVALID, "omega must be in [0, 1)");
   if ((c.nu_pre != 0 && c.nu_pre != 1) || (c.nu_post != 0 && c.nu_post != 1))
     return fail(HMG_E_INVALID, "only one pre- and one post-smoothing sweep are supported");
-  if (c.precision != HMG_FP64 && c.precision != HMG_FP32)
+  if (c.precision != HMG_FP64 && c.precision != HMG_FP32 && c.precision != HMG_MIXED_BF16 &&
+      c.precision != HMG_MIXED_BF16_STENCIL)
     return fail(HMG_E_INVALID, "precision %d is not built in this library", c.precision);
   if (c.levels < 0 || c.replace_every < 0) return fail(HMG_E_INVALID, "bad levels/replace_every");
   grids->clear();
@@ -779,9 +899,13 @@ hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out) {
   ctx->stream = (hipStream_t)hip_stream;
   ctx->g0 = grids[0];
   if (cfg->precision == HMG_FP64)
-    ctx->solver.reset(new Solver<double>(*cfg, ctx->stream, *ec, grids));
+    ctx->solver.reset(new Solver<double, double, double>(*cfg, ctx->stream, *ec, grids));
+  else if (cfg->precision == HMG_FP32)
+    ctx->solver.reset(new Solver<float, float, float>(*cfg, ctx->stream, *ec, grids));
+  else if (cfg->precision == HMG_MIXED_BF16)
+    ctx->solver.reset(new Solver<float, bf16, float>(*cfg, ctx->stream, *ec, grids));
   else
-    ctx->solver.reset(new Solver<float>(*cfg, ctx->stream, *ec, grids));
+    ctx->solver.reset(new Solver<float, bf16, bf16>(*cfg, ctx->stream, *ec, grids));
   delete ec;
   s = ctx->solver->init();
   if (s.code == HMG_OK) {
@@ -897,6 +1021,17 @@ hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev) {
   if (!ctx) return HMG_E_INVALID;
   if (!u_dev) return report(ctx, fail(HMG_E_INVALID, "u_dev is NULL"));
   return report(ctx, ctx->solver->get_disp(u_dev));
+}
+
+hmg_status hmg_warm_start(hmg_ctx ctx, hmg_nn net, double accept_relres, double* relres_out,
+                          int32_t* used_out) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!net || !relres_out || !used_out || !(accept_relres >= 0.0))
+    return report(ctx, fail(HMG_E_INVALID, "bad warm-start arguments"));
+  int used = 0;
+  Status s = ctx->solver->warm_start(*hmg_nn_internal(net), accept_relres, relres_out, &used);
+  *used_out = used;
+  return report(ctx, s);
 }
 
 const char* hmg_last_error(hmg_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }

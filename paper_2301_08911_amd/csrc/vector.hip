@@ -27,6 +27,11 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return s;
 }
 
+template <typename T>
+__device__ __forceinline__ double to_d(T v) {
+  return (double)(typename Acc<T>::type)v;
+}
+
 __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
@@ -53,17 +58,20 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
 
 // r -= alpha q; partials of ||r||^2 and of sum(r) per case and component (the
 // translation component is removed before smoothing).
-template <typename T>
-__global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ r,
+template <typename T, typename V>
+__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
+                                                    const V* __restrict__ p, T* __restrict__ r,
                                                     const T* __restrict__ q, const double* scal,
                                                     Partials part) {
   __shared__ double red[(VB / 64) * NCASE * 4];
   bool on[NCASE];
   T al[NCASE];
+  double al64[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) {
     on[c] = case_on(scal, c);
-    al[c] = (T)scal[S_ALPHA * 8 + c];
+    al64[c] = scal[S_ALPHA * 8 + c];
+    al[c] = (T)al64[c];
   }
   double acc[NCASE * 4];  // [c]: ||r||^2, [6 + 3c + k]: sum r
 #pragma unroll
@@ -77,6 +85,7 @@ __global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ r,
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t o = (int64_t)(c * 3 + k) * n + i;
+        x[o] += al64[c] * to_d(p[o]);
         const T rv = r[o] - al[c] * q[o];
         r[o] = rv;
         acc[c] += (double)rv * (double)rv;
@@ -95,44 +104,20 @@ __global__ void __launch_bounds__(VB) update_kernel(Grid g, T* __restrict__ r,
     }
 }
 
-// x += alpha_x p for every case with a pending step (slot S_XALPHA).
-template <typename T>
-__global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict__ x,
-                                                     const T* __restrict__ p, const double* scal) {
-  double ax[NCASE];
-#pragma unroll
-  for (int c = 0; c < NCASE; ++c) ax[c] = scal[S_XALPHA * 8 + c];
-  const int64_t n = g.n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-#pragma unroll
-    for (int c = 0; c < NCASE; ++c) {
-      if (ax[c] == 0.0) continue;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int64_t o = (int64_t)(c * 3 + k) * n + i;
-        x[o] += ax[c] * (double)p[o];
-      }
-    }
-}
-
-__global__ void clear_xalpha_kernel(double* scal) {
-  if (threadIdx.x < 8) scal[S_XALPHA * 8 + threadIdx.x] = 0.0;
-}
-
 // z = Dinv (r - m), m the per-component mean in `mean` (slots S_MEAN*, may be NULL).
-template <typename T>
-__global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const T* __restrict__ r,
-                                                     const T* __restrict__ dinv, T* __restrict__ z,
+template <typename R, typename D, typename Z>
+__global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const R* __restrict__ r,
+                                                     const D* __restrict__ dinv, Z* __restrict__ z,
                                                      const double* scal, const double* mean) {
+  using A = typename Acc<Z>::type;
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
   const int64_t n = g.n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const T dxx = dinv[i], dyy = dinv[n + i], dzz = dinv[2 * n + i];
-    const T dxy = dinv[3 * n + i], dyz = dinv[4 * n + i], dxz = dinv[5 * n + i];
+    const A dxx = (A)dinv[i], dyy = (A)dinv[n + i], dzz = (A)dinv[2 * n + i];
+    const A dxy = (A)dinv[3 * n + i], dyz = (A)dinv[4 * n + i], dxz = (A)dinv[5 * n + i];
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
@@ -142,12 +127,12 @@ __global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const T* __restrict
         m1 = mean[S_MEAN1 * 8 + c];
         m2 = mean[S_MEAN2 * 8 + c];
       }
-      const T r0 = (T)((double)r[(int64_t)(c * 3 + 0) * n + i] - m0);
-      const T r1 = (T)((double)r[(int64_t)(c * 3 + 1) * n + i] - m1);
-      const T r2 = (T)((double)r[(int64_t)(c * 3 + 2) * n + i] - m2);
-      z[(int64_t)(c * 3 + 0) * n + i] = dxx * r0 + dxy * r1 + dxz * r2;
-      z[(int64_t)(c * 3 + 1) * n + i] = dxy * r0 + dyy * r1 + dyz * r2;
-      z[(int64_t)(c * 3 + 2) * n + i] = dxz * r0 + dyz * r1 + dzz * r2;
+      const A r0 = (A)(to_d(r[(int64_t)(c * 3 + 0) * n + i]) - m0);
+      const A r1 = (A)(to_d(r[(int64_t)(c * 3 + 1) * n + i]) - m1);
+      const A r2 = (A)(to_d(r[(int64_t)(c * 3 + 2) * n + i]) - m2);
+      z[(int64_t)(c * 3 + 0) * n + i] = (Z)(dxx * r0 + dxy * r1 + dxz * r2);
+      z[(int64_t)(c * 3 + 1) * n + i] = (Z)(dxy * r0 + dyy * r1 + dyz * r2);
+      z[(int64_t)(c * 3 + 2) * n + i] = (Z)(dxz * r0 + dyz * r1 + dzz * r2);
     }
   }
 }
@@ -160,6 +145,30 @@ __global__ void fill_kernel(T* __restrict__ a, int64_t count, T v) {
 }
 
 template <typename T>
+__global__ void scale_kernel(T* __restrict__ a, int64_t count, double f) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (T)(to_d(a[i]) * f);
+}
+
+template <typename T>
+__global__ void box_mean_kernel(Grid gf, const T* __restrict__ in, int f, float* __restrict__ out) {
+  const int nx = gf.nx / f, ny = gf.ny / f, nz = gf.nz / f;
+  const int64_t nc = (int64_t)nx * ny * nz;
+  const double inv = 1.0 / ((double)f * f * f);
+  for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < nc;
+       I += (int64_t)gridDim.x * blockDim.x) {
+    const int X = (int)(I % nx), Y = (int)((I / nx) % ny), Z = (int)(I / ((int64_t)nx * ny));
+    double s = 0.0;
+    for (int c = 0; c < f; ++c)
+      for (int b = 0; b < f; ++b)
+        for (int a = 0; a < f; ++a)
+          s += to_d(in[(int64_t)(Z * f + c) * gf.nx * gf.ny + (int64_t)(Y * f + b) * gf.nx + X * f + a]);
+    out[I] = (float)(s * inv);
+  }
+}
+
+template <typename T>
 __global__ void pattern_kernel(T* __restrict__ a, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -167,7 +176,7 @@ __global__ void pattern_kernel(T* __restrict__ a, int64_t count) {
     h ^= h >> 15;
     h *= 2246822519u;
     h ^= h >> 13;
-    a[i] = (T)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+    a[i] = (T)(typename Acc<T>::type)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
   }
 }
 
@@ -175,7 +184,7 @@ template <typename S, typename D>
 __global__ void convert_kernel(D* __restrict__ d, const S* __restrict__ s, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
-    d[i] = (D)s[i];
+    d[i] = (D)(typename Acc<D>::type)to_d(s[i]);
 }
 
 template <typename T>
@@ -185,9 +194,9 @@ __global__ void copy_kernel(T* __restrict__ d, const T* __restrict__ s, int64_t 
     d[i] = s[i];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(VB) dot_kernel(Grid g, const T* __restrict__ a,
-                                                 const T* __restrict__ b, const double* scal,
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(VB) dot_kernel(Grid g, const TA* __restrict__ a,
+                                                 const TB* __restrict__ b, const double* scal,
                                                  Partials part, int slot) {
   __shared__ double red[VB / 64];
   double acc[NCASE];
@@ -202,7 +211,7 @@ __global__ void __launch_bounds__(VB) dot_kernel(Grid g, const T* __restrict__ a
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const int64_t o = (int64_t)(c * 3 + k) * n + i;
-        acc[c] += (double)a[o] * (double)b[o];
+        acc[c] += to_d(a[o]) * to_d(b[o]);
       }
     }
 #pragma unroll
@@ -221,7 +230,7 @@ __global__ void __launch_bounds__(VB) mean_partial_kernel(Grid g, const T* __res
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-      acc += (double)a[(int64_t)ck * n + i];
+      acc += to_d(a[(int64_t)ck * n + i]);
     const double t = block_sum<VB / 64>(acc, red);
     const int c = ck / 3, k = ck % 3;
     if (threadIdx.x == 0) part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = t;
@@ -269,7 +278,6 @@ __global__ void fin_init_kernel(double* scal, double eps_abs, double tol) {
   scal[S_ALPHA * 8 + c] = 0.0;
   scal[S_BETA * 8 + c] = 0.0;
   scal[S_RZ * 8 + c] = 0.0;
-  scal[S_XALPHA * 8 + c] = 0.0;
 }
 
 __global__ void fin_alpha_kernel(double* scal) {
@@ -279,18 +287,28 @@ __global__ void fin_alpha_kernel(double* scal) {
   const bool on = scal[S_ACTIVE * 8 + c] != 0.0 && pq != 0.0;
   const double a = on ? scal[S_RZ * 8 + c] / pq : 0.0;
   scal[S_ALPHA * 8 + c] = a;
-  scal[S_XALPHA * 8 + c] = a;  // applied to x by the next matvec or a flush
 }
 
-__global__ void fin_beta_kernel(double* scal) {
+__global__ void fin_beta_kernel(double* scal, int pr) {
   const int c = threadIdx.x;
   if (c >= NCASE) return;
   if (scal[S_ACTIVE * 8 + c] == 0.0) return;
   const double rz = scal[S_RZ * 8 + c], rzn = scal[S_RZNEW * 8 + c];
   const bool restart = scal[S_RESTART * 8 + c] != 0.0;
-  scal[S_BETA * 8 + c] = (rz != 0.0 && !restart) ? rzn / rz : 0.0;
+  double beta = 0.0;
+  if (rz != 0.0 && !restart) {
+    if (pr && scal[S_REPLACED * 8 + c] == 0.0) {
+      // (r_new - r_old).z_new = -alpha q.z_new; negative values restart
+      beta = -scal[S_ALPHA * 8 + c] * scal[S_QZ * 8 + c] / rz;
+      if (beta < 0.0) beta = 0.0;
+    } else {
+      beta = rzn / rz;
+    }
+  }
+  scal[S_BETA * 8 + c] = beta;
   scal[S_RZ * 8 + c] = rzn;
   scal[S_RESTART * 8 + c] = 0.0;
+  scal[S_REPLACED * 8 + c] = 0.0;
 }
 
 __global__ void fin_mean_kernel(Partials part, int nblk, int64_t n, double* scal) {
@@ -310,7 +328,7 @@ __global__ void all_active_kernel(double* scal) {
     scal[S_BETA * 8 + c] = 0.0;
     scal[S_ALPHA * 8 + c] = 0.0;
     scal[S_RESTART * 8 + c] = 0.0;
-    scal[S_XALPHA * 8 + c] = 0.0;
+    scal[S_REPLACED * 8 + c] = 0.0;
   }
 }
 
@@ -351,29 +369,56 @@ void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st) {
 template void vec_convert<float, double>(double*, const float*, int64_t, hipStream_t);
 template void vec_convert<double, float>(float*, const double*, int64_t, hipStream_t);
 template void vec_convert<double, double>(double*, const double*, int64_t, hipStream_t);
+template void vec_convert<float, float>(float*, const float*, int64_t, hipStream_t);
+template void vec_convert<float, bf16>(bf16*, const float*, int64_t, hipStream_t);
+template void vec_convert<bf16, float>(float*, const bf16*, int64_t, hipStream_t);
+template void vec_convert<bf16, double>(double*, const bf16*, int64_t, hipStream_t);
 
-template <typename T>
-void vec_flush_x(const Grid& g, double* x, const T* p, double* scal, hipStream_t st) {
-  hipLaunchKernelGGL(flush_x_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, x, p, scal);
-  hipLaunchKernelGGL(clear_xalpha_kernel, dim3(1), dim3(64), 0, st, scal);
-}
-
-template <typename T>
-void vec_update_r(const Grid& g, T* r, const T* q, const double* scal, Partials part,
-                  int* nblk_out, hipStream_t st) {
+template <typename T, typename V>
+void vec_update_r(const Grid& g, double* x, const V* p, T* r, const T* q, const double* scal,
+                  Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL(update_kernel<T>, dim3(nb), dim3(VB), 0, st, g, r, q, scal, part);
+  hipLaunchKernelGGL((update_kernel<T, V>), dim3(nb), dim3(VB), 0, st, g, x, p, r, q, scal, part);
   *nblk_out = nb;
 }
-template <typename T>
-void vec_jacobi0(const Grid& g, const T* r, const T* dinv, T* z, const double* scal,
+template void vec_update_r<float, float>(const Grid&, double*, const float*, float*, const float*,
+                                         const double*, Partials, int*, hipStream_t);
+template void vec_update_r<double, double>(const Grid&, double*, const double*, double*,
+                                           const double*, const double*, Partials, int*,
+                                           hipStream_t);
+template void vec_update_r<float, bf16>(const Grid&, double*, const bf16*, float*, const float*,
+                                        const double*, Partials, int*, hipStream_t);
+
+template <typename R, typename D, typename Z>
+void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,
                  const double* mean, hipStream_t st) {
-  hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(blocks_for(g.n)), dim3(VB), 0, st, g, r, dinv, z,
-                     scal, mean);
+  hipLaunchKernelGGL((jacobi0_kernel<R, D, Z>), dim3(blocks_for(g.n)), dim3(VB), 0, st, g, r,
+                     dinv, z, scal, mean);
 }
+template void vec_jacobi0<float, float, float>(const Grid&, const float*, const float*, float*,
+                                               const double*, const double*, hipStream_t);
+template void vec_jacobi0<double, double, double>(const Grid&, const double*, const double*,
+                                                  double*, const double*, const double*,
+                                                  hipStream_t);
+template void vec_jacobi0<float, float, bf16>(const Grid&, const float*, const float*, bf16*,
+                                              const double*, const double*, hipStream_t);
+template void vec_jacobi0<bf16, bf16, bf16>(const Grid&, const bf16*, const bf16*, bf16*,
+                                            const double*, const double*, hipStream_t);
+template void vec_jacobi0<bf16, float, bf16>(const Grid&, const bf16*, const float*, bf16*,
+                                             const double*, const double*, hipStream_t);
+
 template <typename T>
 void vec_fill(T* a, int64_t count, T v, hipStream_t st) {
   hipLaunchKernelGGL(fill_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count, v);
+}
+template <typename T>
+void vec_scale(T* a, int64_t count, double factor, hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count, factor);
+}
+template <typename T>
+void vec_box_mean(const Grid& gf, const T* in, int f, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(box_mean_kernel<T>, dim3(blocks_for(gf.n / ((int64_t)f * f * f))), dim3(VB), 0,
+                     st, gf, in, f, out);
 }
 template <typename T>
 void vec_pattern(T* a, int64_t count, hipStream_t st) {
@@ -383,13 +428,15 @@ template <typename T>
 void vec_copy(T* d, const T* s, int64_t count, hipStream_t st) {
   hipLaunchKernelGGL(copy_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, d, s, count);
 }
-template <typename T>
-void vec_dot_cases(const Grid& g, const T* a, const T* b, const double* scal, Partials part,
+template <typename TA, typename TB>
+void vec_dot_cases(const Grid& g, const TA* a, const TB* b, const double* scal, Partials part,
                    int slot, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL(dot_kernel<T>, dim3(nb), dim3(VB), 0, st, g, a, b, scal, part, slot);
+  hipLaunchKernelGGL((dot_kernel<TA, TB>), dim3(nb), dim3(VB), 0, st, g, a, b, scal, part, slot);
   *nblk_out = nb;
 }
+template void vec_dot_cases<float, bf16>(const Grid&, const float*, const bf16*, const double*,
+                                         Partials, int, int*, hipStream_t);
 template <typename T>
 void vec_mean_partial(const Grid& g, const T* a, Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
@@ -419,8 +466,8 @@ void fin_init(double* scal, double eps_abs, double tol, hipStream_t st) {
 void fin_alpha(double* scal, hipStream_t st) {
   hipLaunchKernelGGL(fin_alpha_kernel, dim3(1), dim3(64), 0, st, scal);
 }
-void fin_beta(double* scal, hipStream_t st) {
-  hipLaunchKernelGGL(fin_beta_kernel, dim3(1), dim3(64), 0, st, scal);
+void fin_beta(double* scal, bool polak_ribiere, hipStream_t st) {
+  hipLaunchKernelGGL(fin_beta_kernel, dim3(1), dim3(64), 0, st, scal, polak_ribiere ? 1 : 0);
 }
 void fin_mean(const Partials& part, int nblk, int64_t n, double* scal, hipStream_t st) {
   hipLaunchKernelGGL(fin_mean_kernel, dim3(NCASE * 3), dim3(256), 0, st, part, nblk, n, scal);
@@ -430,21 +477,19 @@ void scal_set_all_active(double* scal, hipStream_t st) {
 }
 
 #define HMG_INST(T)                                                                             \
-  template void vec_update_r<T>(const Grid&, T*, const T*, const double*, Partials, int*,        \
-                                hipStream_t);                                                   \
-  template void vec_flush_x<T>(const Grid&, double*, const T*, double*, hipStream_t);           \
-  template void vec_jacobi0<T>(const Grid&, const T*, const T*, T*, const double*,              \
-                               const double*, hipStream_t);                                     \
   template void vec_fill<T>(T*, int64_t, T, hipStream_t);                                       \
+  template void vec_scale<T>(T*, int64_t, double, hipStream_t);                                 \
+  template void vec_box_mean<T>(const Grid&, const T*, int, float*, hipStream_t);               \
   template void vec_pattern<T>(T*, int64_t, hipStream_t);                                       \
   template void vec_copy<T>(T*, const T*, int64_t, hipStream_t);                                \
-  template void vec_dot_cases<T>(const Grid&, const T*, const T*, const double*, Partials, int,  \
+  template void vec_dot_cases<T, T>(const Grid&, const T*, const T*, const double*, Partials, int,\
                                  int*, hipStream_t);                                            \
   template void vec_mean_partial<T>(const Grid&, const T*, Partials, int*, hipStream_t);        \
   template void vec_mean_subtract<T>(const Grid&, T*, const double*, hipStream_t);        \
   template void vec_sum_scalar<T>(const T*, int64_t, double*, Partials, hipStream_t);
 HMG_INST(float)
 HMG_INST(double)
+HMG_INST(bf16)
 #undef HMG_INST
 
 }  // namespace hmg

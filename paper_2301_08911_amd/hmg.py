@@ -15,8 +15,9 @@ import torch
 from . import _lib
 
 OK, E_INVALID, E_OOM, E_DEVICE, E_NOT_CONVERGED, E_STATE = range(6)
-KERNELS = {"matvec": 0, "residual": 1, "post_smooth": 2, "update": 3, "true_residual": 4}
-PRECISIONS = {"fp64": 0, "fp32": 1, "mixed_bf16": 2, "mixed_fp16": 3}
+KERNELS = {"matvec": 0, "residual": 1, "post_smooth": 2, "update": 3, "true_residual": 4,
+           "jacobi": 5}
+PRECISIONS = {"fp64": 0, "fp32": 1, "mixed_bf16": 2, "mixed_bf16_stencil": 4}
 
 
 class HmgError(RuntimeError):
@@ -40,7 +41,8 @@ class Context:
     """One periodic cell on the current GPU (``hmg_create`` / ``hmg_destroy``)."""
 
     def __init__(self, shape, *, E0=1.0, nu=0.3, penal=3.0, Emin=1e-9, levels=0, omega=0.0,
-                 precision="fp32", replace_every=0, stream: torch.cuda.Stream | None = None):
+                 precision="fp32", replace_every=None,
+                 stream: torch.cuda.Stream | None = None):
         self.lib = _lib.load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -49,6 +51,8 @@ class Context:
         self.field_dtype = torch.float64 if precision == "fp64" else torch.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if replace_every is None:  # the mixed form recomputes r in FP64 every 20 iterations
+            replace_every = 20 if precision.startswith("mixed") else 0
         cfg = _lib.HmgConfig(nx, ny, nz, E0, nu, penal, Emin, levels, omega, 1, 1,
                              PRECISIONS[precision], replace_every)
         self.config = cfg

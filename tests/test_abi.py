@@ -6,13 +6,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hmg.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("hmg.h", "hmg_nn.h")]
 
 
 def declared_symbols():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hmg_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(hmg_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -44,7 +47,7 @@ def test_config_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\nint main(void){\n'
                     'printf("%%zu", sizeof(hmg_config));\n%s\nreturn 0;}\n' % (
-                        HEADER, "".join('printf(" %%zu", offsetof(hmg_config, %s));' % f
+                        HEADERS[0], "".join('printf(" %%zu", offsetof(hmg_config, %s));' % f
                                         for f in fields)))
     exe = tmp_path / "layout"
     subprocess.run([cc, str(prog), "-o", str(exe)], check=True)

@@ -1,0 +1,163 @@
+"""GPU parity of the reduced-precision forms (bf16 storage, FP32 arithmetic).
+
+mixed_bf16 streams the multigrid preconditioner's vectors in bf16 (round to
+nearest even, relative error at most 2^-8) and computes in FP32; the outer PCG
+vectors are FP32, the iterate, dots, residual recomputation and coarsest solve
+FP64.  mixed_bf16_stencil also stores the coarse stencils in bf16.  Converged
+C^H must match the FP64 oracle to 1e-4 relative (the reduced-precision bar);
+stored stencils and transfers are checked against the oracle's sparse products
+within the bf16 rounding bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hmgref as O
+from paper_2301_08911_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+K0 = O.element_stiffness()
+CHI = O.unit_strain_displacements()
+BF16_EPS = 2.0 ** -8  # unit roundoff of bf16 (8 significant bits), round to nearest
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def ctx_for(shape, precision="mixed_bf16", **kw):
+    from paper_2301_08911_amd.hmg import Context
+    return Context(shape, precision=precision, **kw)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def f32(rho):
+    return np.asarray(rho, dtype=np.float32).ravel()
+
+
+def bf16_round(a):
+    """Round float64 values to bf16 (nearest even) and back, via torch on the CPU."""
+    return torch.from_numpy(np.asarray(a, np.float64)).to(torch.bfloat16).double().numpy()
+
+
+def test_mixed_first_coarse_stencil_is_rounded_ptkp():
+    shape = (16, 8, 24)
+    print(f"mixed stencil {shape}", flush=True)
+    rho = f32(I.uniform_density(shape, 5))
+    ctx = ctx_for(shape, "mixed_bf16_stencil")
+    ctx.set_density(dev(rho))
+    s = O.simp_scale(rho.astype(np.float64))
+    K = O.assemble_stiffness(s, shape, K0)
+    P = O.prolongation(shape)
+    coarse = tuple(v // 2 for v in shape)
+    ref = O.stencil_blocks((P.T @ K @ P).tocsr(), coarse)
+    st = ctx.get_stencil(1).cpu().numpy().astype(np.float64)
+    # level 1 is assembled in FP64 and rounded once
+    tiny = 1e-12 * np.abs(ref).max()
+    assert np.all(np.abs(st - ref) <= BF16_EPS * np.abs(ref) + tiny)
+    # deeper levels are assembled from the rounded finer stencils
+    Kc = (P.T @ K @ P).tocsr()
+    fine = coarse
+    for level in range(2, ctx.num_levels()):
+        Pl = O.prolongation(fine)
+        Kc = (Pl.T @ Kc @ Pl).tocsr()
+        fine = tuple(v // 2 for v in fine)
+        refl = O.stencil_blocks(Kc, fine)
+        stl = ctx.get_stencil(level).cpu().numpy().astype(np.float64)
+        err = np.abs(stl - refl).max() / np.abs(refl).max()
+        assert err < 8 * BF16_EPS, (level, err)
+
+
+def test_mixed_transfers_match_sparse_P():
+    shape = (16, 8, 12)
+    ctx = ctx_for(shape)
+    ctx.set_density(dev(np.full(np.prod(shape), 0.5, np.float32)))
+    P = O.prolongation(shape)
+    nf, nc = np.prod(shape), np.prod(shape) // 8
+    e = bf16_round(I.random_signed_field(tuple(v // 2 for v in shape), 6))
+    r = bf16_round(I.random_signed_field(shape, 7))
+    up = ctx.transfer(0, 1, dev(e)).cpu().numpy().astype(np.float64)
+    dn = ctx.transfer(0, 0, dev(r)).cpu().numpy().astype(np.float64)
+    up_ref = (P @ e.transpose(0, 2, 1).reshape(6, 3 * nc).T).T.reshape(6, nf, 3).transpose(0, 2, 1)
+    dn_ref = (P.T @ r.transpose(0, 2, 1).reshape(6, 3 * nf).T).T.reshape(6, nc, 3).transpose(0, 2, 1)
+    # sums of bf16 inputs in FP32, rounded once to bf16 on output
+    assert np.all(np.abs(up - up_ref) <= BF16_EPS * np.abs(up_ref) + 1e-6)
+    assert np.all(np.abs(dn - dn_ref) <= BF16_EPS * np.abs(dn_ref) + 1e-5)
+
+
+def oracle_solution(rho, shape):
+    s = O.simp_scale(rho)
+    u, _, _ = O.solve_cases(s, shape, tol=1e-10)
+    return u, O.elastic_tensor(s, u, shape, K0, CHI)
+
+
+@pytest.mark.parametrize("shape,seed,prec", [((16, 16, 16), 11, "mixed_bf16"),
+                                             ((24, 24, 24), 12, "mixed_bf16"),
+                                             ((16, 24, 8), 13, "mixed_bf16"),
+                                             ((16, 16, 16), 11, "mixed_bf16_stencil"),
+                                             ((32, 32, 32), 14, "mixed_bf16_stencil")])
+def test_mixed_tensor_within_1e4(shape, seed, prec):
+    print(f"mixed C^H {shape} {prec}", flush=True)
+    rho = f32(I.smoothed_noise_density(shape, seed, 0.3, sigma=2.0))
+    ctx = ctx_for(shape, prec)
+    ctx.set_density(dev(rho))
+    res = ctx.solve_cases(1e-6, 400)
+    assert res.converged, res
+    assert (res.relres <= 1e-6).all(), res.relres
+    C = ctx.elastic_tensor()
+    u, Cref = oracle_solution(rho.astype(np.float64), shape)
+    assert rel(C, Cref) < 1e-4, rel(C, Cref)
+    g = ctx.sensitivity(O.bulk_weights()).cpu().numpy().astype(np.float64)
+    gref = O.sensitivity(rho.astype(np.float64), u, shape, K0, CHI, O.bulk_weights())
+    assert rel(g, gref) < 1e-2, rel(g, gref)
+
+
+def test_mixed_laminate_closed_form():
+    shape = (64, 64, 64)
+    nz = shape[2]
+    prof = np.where((np.arange(nz) // 3) % 2 == 0, 1.0, 0.2).astype(np.float32)
+    rho = f32(I.z_laminate(shape, prof))
+    ctx = ctx_for(shape)
+    ctx.set_density(dev(rho))
+    res = ctx.solve_cases(1e-6, 400)
+    assert res.converged, res
+    s = O.simp_scale(prof.astype(np.float64))
+    lam, mu = O.lame(1.0, 0.3)
+    a, H, c = np.mean(s), 1.0 / np.mean(1.0 / s), 0.3 / 0.7
+    ref = np.zeros((6, 6))
+    ref[0, 0] = ref[1, 1] = a * (lam + 2 * mu - c * lam) + c * H * lam
+    ref[0, 1] = ref[1, 0] = a * (1 - c) * lam + c * H * lam
+    ref[2, 2] = H * (lam + 2 * mu)
+    ref[0, 2] = ref[2, 0] = ref[1, 2] = ref[2, 1] = H * lam
+    ref[3, 3] = a * mu
+    ref[4, 4] = ref[5, 5] = H * mu
+    assert rel(ctx.elastic_tensor(), ref) < 1e-4
+
+
+def test_mixed_matches_fp32_on_soft_contrast_cell():
+    """Emin = 1e-9 with a 1e-3 floor: the corrections span ~9 decades; the mixed
+    form must still converge and agree with the FP32 form to 1e-4."""
+    shape = (64, 64, 64)
+    rho = f32(I.smoothed_noise_density(shape, 3, 0.3, sigma=2.0))
+    out = {}
+    for prec in ("fp32", "mixed_bf16"):
+        ctx = ctx_for(shape, prec)
+        ctx.set_density(dev(rho))
+        res = ctx.solve_cases(1e-6, 600)
+        print(prec, res.iters.tolist(), flush=True)
+        assert res.converged, (prec, res)
+        out[prec] = (ctx.elastic_tensor(), res.iters)
+    assert rel(out["mixed_bf16"][0], out["fp32"][0]) < 1e-4
+    # bf16 preconditioner vectors cost at most a few iterations
+    assert out["mixed_bf16"][1].max() <= 1.2 * out["fp32"][1].max() + 10

@@ -1,0 +1,178 @@
+"""GPU parity of the warm-start network kernels against the FP64 oracle.
+
+The convolutions run on the matrix cores with bf16 operands and FP32
+accumulation.  Inputs and weights are rounded to bf16 on the host first, so the
+single-layer checks compare exactly representable operands and only the
+accumulation order differs (tolerance 1e-5).  A whole network rounds every
+convolution operand to bf16; the oracle network does the same rounding (sums in
+FP64), so the two agree to FP32 accumulation order, up to the rare activation
+whose sign the order flips at a ReLU (1e-3 forward, 1e-2 gradient).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nnref as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def bf16(a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).float().numpy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+CASES = [  # B, Cin, Cout, (D, H, W)
+    (2, 3, 5, (8, 4, 16)),
+    (1, 1, 8, (8, 8, 8)),
+    (2, 8, 18, (4, 8, 8)),
+    (1, 96, 32, (4, 4, 4)),
+    (1, 24, 8, (8, 8, 8)),
+    (3, 4, 6, (2, 2, 2)),   # 8 voxels per sample: waves span samples, ragged tail
+    (1, 5, 3, (3, 5, 7)),   # odd extents
+]
+
+
+@pytest.mark.parametrize("B,Cin,Cout,dims", CASES)
+def test_conv_forward_matches_oracle(B, Cin, Cout, dims):
+    from paper_2301_08911_amd import nn
+    print(f"conv fwd {B} {Cin}->{Cout} {dims}", flush=True)
+    r = np.random.default_rng(Cin * 100 + Cout)
+    x = bf16(r.standard_normal((B, Cin) + dims))
+    w = bf16(r.standard_normal((Cout, Cin, 27)) / np.sqrt(27 * Cin))
+    b = r.standard_normal(Cout).astype(np.float32)
+    y = nn.conv3d_forward(dev(x), dev(w), dev(b)).cpu().numpy()
+    ref = N.conv3d(x.astype(np.float64), w.astype(np.float64), b.astype(np.float64))
+    assert np.abs(y - ref).max() < 1e-5 * np.abs(ref).max()
+    yr = nn.conv3d_forward(dev(x), dev(w), dev(b), relu=True).cpu().numpy()
+    assert np.abs(yr - np.maximum(ref, 0)).max() < 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("B,Cin,Cout,dims", CASES)
+def test_conv_backward_data_matches_oracle(B, Cin, Cout, dims):
+    from paper_2301_08911_amd import nn
+    r = np.random.default_rng(Cin * 7 + Cout)
+    dz = bf16(r.standard_normal((B, Cout) + dims))
+    w = bf16(r.standard_normal((Cout, Cin, 27)) / np.sqrt(27 * Cout))
+    base = r.standard_normal((B, Cin) + dims).astype(np.float32)  # dx accumulates
+    dx = nn.conv3d_backward_data(dev(dz), dev(w), dev(base)).cpu().numpy()
+    ref = base + N.conv3d_backward_data(dz.astype(np.float64), w.astype(np.float64))
+    assert np.abs(dx - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("B,Cin,Cout,dims", CASES)
+def test_conv_backward_weight_matches_oracle(B, Cin, Cout, dims):
+    from paper_2301_08911_amd import nn
+    r = np.random.default_rng(Cin * 11 + Cout)
+    x = bf16(r.standard_normal((B, Cin) + dims))
+    dz = bf16(r.standard_normal((B, Cout) + dims))
+    dw0 = r.standard_normal((Cout, Cin, 27)).astype(np.float32)
+    db0 = r.standard_normal(Cout).astype(np.float32)
+    dw, db = nn.conv3d_backward_weight(dev(x), dev(dz), dev(dw0), dev(db0))
+    rw, rb = N.conv3d_backward_weight(x.astype(np.float64), dz.astype(np.float64))
+    assert np.abs(dw.cpu().numpy() - (dw0 + rw)).max() < 1e-5 * np.abs(rw).max()
+    assert np.abs(db.cpu().numpy() - (db0 + rb)).max() < 1e-5 * np.abs(rb).max()
+
+
+def small_net(levels=3, base=4):
+    from paper_2301_08911_amd import nn
+    net = nn.Net(levels=levels, base_channels=base, in_channels=1, out_channels=18, seed=5)
+    ref = N.UNetRef(levels=levels, base=base, cin=1, cout=18, operand_round=N.round_bf16)
+    assert net.param_count == ref.nparam
+    r = np.random.default_rng(3)
+    p = np.zeros(ref.nparam)
+    for k, (ci, co, _) in enumerate(ref.convs):
+        p[ref.woff[k]:ref.woff[k] + co * ci * 27] = r.standard_normal(co * ci * 27) * np.sqrt(2.0 / (27 * ci))
+        # positive biases keep pre-activations away from the ReLU kink, where
+        # FP32 and FP64 accumulation orders could disagree on the sign
+        p[ref.boff[k]:ref.boff[k] + co] = 0.5 + 0.1 * r.standard_normal(co)
+    p = bf16(p).astype(np.float64)
+    net.set_params(p.astype(np.float32))
+    return net, ref, p
+
+
+def test_network_forward_and_gradients_match_oracle():
+    net, ref, p = small_net()
+    r = np.random.default_rng(4)
+    D, B = 8, 2
+    x = bf16(r.random((B, 1, D, D, D)))
+    y = net.forward(dev(x)).cpu().numpy()
+    yref, cache = ref.forward(p, x.astype(np.float64))
+    assert rel(y, yref) < 1e-3, rel(y, yref)
+    dy = r.standard_normal(yref.shape)
+    net.zero_grad()
+    net.backward(dev(dy))
+    g = net.get_grads().astype(np.float64)
+    gref, _ = ref.backward(p, cache, dy)
+    assert rel(g, gref) < 1e-2, rel(g, gref)
+    # per layer: every weight and bias block individually
+    for k, (ci, co, _) in enumerate(ref.convs):
+        sw = slice(ref.woff[k], ref.woff[k] + co * ci * 27)
+        sb = slice(ref.boff[k], ref.boff[k] + co)
+        assert rel(g[sw], gref[sw]) < 2e-2, (k, rel(g[sw], gref[sw]))
+        assert rel(g[sb], gref[sb]) < 2e-2, (k, rel(g[sb], gref[sb]))
+    # a second backward accumulates
+    net.backward(dev(dy))
+    assert rel(net.get_grads(), 2 * g) < 1e-6
+
+
+def test_adam_reduces_loss_on_a_fixed_batch():
+    net, ref, p = small_net(levels=2, base=4)
+    r = np.random.default_rng(8)
+    x = dev(r.random((2, 1, 8, 8, 8)))
+    t = dev(0.1 * r.standard_normal((2, 18, 8, 8, 8)))
+    y = torch.empty_like(t)
+    dy = torch.empty_like(t)
+    losses = []
+    for step in range(1, 61):
+        net.forward(x, out=y)
+        losses.append(net.mse(y, t, dy))
+        net.zero_grad()
+        net.backward(dy)
+        net.adam_step(3e-3, step)
+    assert losses[-1] < 0.7 * losses[0], losses[::10]
+
+
+def test_mse_matches_definition():
+    from paper_2301_08911_amd import nn
+    net = nn.Net(levels=1, base_channels=2, in_channels=1, out_channels=1)
+    r = np.random.default_rng(9)
+    y, t = r.standard_normal(1000).astype(np.float32), r.standard_normal(1000).astype(np.float32)
+    dy = torch.empty(1000, device="cuda")
+    loss = net.mse(dev(y), dev(t), dy)
+    assert abs(loss - np.mean((y.astype(np.float64) - t) ** 2)) < 1e-6 * loss
+    assert np.abs(dy.cpu().numpy() - 2 * (y - t) / 1000).max() < 1e-7
+
+
+def test_warm_start_falls_back_on_a_poor_guess():
+    from paper_2301_08911_amd import inputs as I, nn
+    from paper_2301_08911_amd.hmg import Context
+    shape = (32, 32, 32)
+    rho = I.smoothed_noise_density(shape, 30, 0.3, sigma=1.5).astype(np.float32).ravel()
+    ctx = Context(shape, precision="fp32")
+    ctx.set_density(dev(rho))
+    net = nn.Net(seed=1)
+    net.set_params(np.zeros(net.param_count, np.float32))  # predicts u = 0
+    rr, used = nn.warm_start(ctx, net, 0.5)
+    assert abs(rr - 1.0) < 1e-6 and not used
+    res = ctx.solve_cases(1e-6, 400, init=1)
+    assert res.converged
+    cold = Context(shape, precision="fp32")
+    cold.set_density(dev(rho))
+    res0 = cold.solve_cases(1e-6, 400)
+    assert (res.iters == res0.iters).all()
+    assert np.abs(ctx.elastic_tensor() - cold.elastic_tensor()).max() < 1e-12
