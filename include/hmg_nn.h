@@ -79,12 +79,15 @@ hmg_status hmg_nn_mse(hmg_nn net, const float* y_dev, const float* t_dev, int64_
 /* Warm start of a solver context (cubic cells only): box-mean the density set
  * by hmg_set_density onto the multigrid level whose size is the largest of
  * N, N/2, ... not above 64 (and divisible by 2^(levels-1)), predict u / N
- * there, multiply by N, remove the per-component mean and prolongate to the
- * fine grid with the solver's trilinear P.  The guess is kept as the iterate
- * of the next hmg_solve_cases(init = 1) when its relative residual
- * ||f - K u|| / ||f|| (FP64, worst case over the six cases) is at most
- * accept_relres; otherwise the iterate is reset to zero (cold start).
- * relres_out receives the worst relative residual, used_out 1 or 0. */
+ * there, multiply by N, remove the per-component mean, prolongate to the fine
+ * grid with the solver's trilinear P, and apply one multigrid correction
+ * u += M (f - K u) (a prediction that is right at low frequencies still
+ * carries a large high-frequency residual on the fine grid, which one cycle
+ * removes).  The result is kept as the iterate of the next
+ * hmg_solve_cases(init = 1) when its relative residual ||f - K u|| / ||f||
+ * (FP64, worst case over the six cases) is at most accept_relres; otherwise
+ * the iterate is reset to zero (cold start).  relres_out receives that worst
+ * relative residual, used_out 1 or 0. */
 hmg_status hmg_warm_start(hmg_ctx ctx, hmg_nn net, double accept_relres, double* relres_out,
                           int32_t* used_out);
 

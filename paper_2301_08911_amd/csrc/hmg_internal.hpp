@@ -158,6 +158,9 @@ template <typename T>
 void vec_fill(T* a, int64_t count, T v, hipStream_t st);
 template <typename T>
 void vec_scale(T* a, int64_t count, double factor, hipStream_t st);
+// x (FP64) += z
+template <typename T>
+void vec_add_to(double* x, const T* z, int64_t count, hipStream_t st);
 // out[V] = mean of in over the f^3 fine cells of coarse cell V (gf.nx/f cells per axis).
 template <typename T>
 void vec_box_mean(const Grid& gf, const T* in, int f, float* out, hipStream_t st);

@@ -329,21 +329,36 @@ class Solver final : public SolverIface {
       prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, nullptr, true, st_);
       vec_convert<T, double>(x_, w0_, F, st_);
     }
+    // relative residual of the guess, then of the guess after one V-cycle
+    // correction x += M (f - K x): a guess right at low frequencies can carry a
+    // large high-frequency residual, which a single cycle removes
     Op0Launch<double> L64{g0, mk64_, s64_, st_};
-    scal_set_all_active(aux_, st_);
-    op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
-    fin_sum(part_, S_FF, nb, aux_, true, st_);
-    fin_sum(part_, S_TRUE, nb, aux_, true, st_);
-    HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
-    const double* ha = hscal_ + S_NSLOT * 8;
     const double lam1 = cfg_.nu / ((1 + cfg_.nu) * (1 - 2 * cfg_.nu));
     const double mu1 = 1.0 / (2 * (1 + cfg_.nu));
     const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * mean_s_;
-    double worst = 0.0;
-    for (int c = 0; c < NCASE; ++c) {
-      const double ff = std::sqrt(ha[S_FF * 8 + c]), tr = std::sqrt(ha[S_TRUE * 8 + c]);
-      if (ff > eps_abs) worst = std::max(worst, tr / ff);
-    }
+    auto worst_relres = [&](double* out) -> Status {
+      scal_set_all_active(aux_, st_);
+      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
+      fin_sum(part_, S_FF, nb, aux_, true, st_);
+      fin_sum(part_, S_TRUE, nb, aux_, true, st_);
+      HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+      const double* ha = hscal_ + S_NSLOT * 8;
+      double w = 0.0;
+      for (int c = 0; c < NCASE; ++c) {
+        const double ff = std::sqrt(ha[S_FF * 8 + c]), tr = std::sqrt(ha[S_TRUE * 8 + c]);
+        if (ff > eps_abs) w = std::max(w, tr / ff);
+      }
+      *out = w;
+      return Status{};
+    };
+    double raw = 0.0, worst = 0.0;
+    HMG_TRY(worst_relres(&raw));
+    vec_mean_partial<T>(g0, r_, part_, &nb, st_);
+    fin_mean(part_, nb, g0.n, aux_, st_);
+    HMG_TRY(vcycle_apply(r_, z_, nullptr, aux_, &nb));
+    vec_add_to<T>(x_, z_, F, st_);
+    HMG_TRY(worst_relres(&worst));
+    raw_relres_ = raw;
     *relres = worst;
     *used = worst <= accept ? 1 : 0;
     if (*used) {
@@ -812,6 +827,7 @@ class Solver final : public SolverIface {
   bool have_solution_ = false;  // x_ solves the current density (C^H, sensitivities)
   bool have_iterate_ = false;   // x_ holds a solution or an accepted guess (init = 1)
   float* nnbuf_ = nullptr;      // warm start: network input and output (<= 64^3)
+  double raw_relres_ = 0.0;     // warm start: relative residual before the correction cycle
 };
 
 }  // namespace

@@ -152,6 +152,13 @@ __global__ void scale_kernel(T* __restrict__ a, int64_t count, double f) {
 }
 
 template <typename T>
+__global__ void add_to_kernel(double* __restrict__ x, const T* __restrict__ z, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += to_d(z[i]);
+}
+
+template <typename T>
 __global__ void box_mean_kernel(Grid gf, const T* __restrict__ in, int f, float* __restrict__ out) {
   const int nx = gf.nx / f, ny = gf.ny / f, nz = gf.nz / f;
   const int64_t nc = (int64_t)nx * ny * nz;
@@ -416,6 +423,10 @@ void vec_scale(T* a, int64_t count, double factor, hipStream_t st) {
   hipLaunchKernelGGL(scale_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, a, count, factor);
 }
 template <typename T>
+void vec_add_to(double* x, const T* z, int64_t count, hipStream_t st) {
+  hipLaunchKernelGGL(add_to_kernel<T>, dim3(blocks_for(count)), dim3(VB), 0, st, x, z, count);
+}
+template <typename T>
 void vec_box_mean(const Grid& gf, const T* in, int f, float* out, hipStream_t st) {
   hipLaunchKernelGGL(box_mean_kernel<T>, dim3(blocks_for(gf.n / ((int64_t)f * f * f))), dim3(VB), 0,
                      st, gf, in, f, out);
@@ -479,6 +490,7 @@ void scal_set_all_active(double* scal, hipStream_t st) {
 #define HMG_INST(T)                                                                             \
   template void vec_fill<T>(T*, int64_t, T, hipStream_t);                                       \
   template void vec_scale<T>(T*, int64_t, double, hipStream_t);                                 \
+  template void vec_add_to<T>(double*, const T*, int64_t, hipStream_t);                         \
   template void vec_box_mean<T>(const Grid&, const T*, int, float*, hipStream_t);               \
   template void vec_pattern<T>(T*, int64_t, hipStream_t);                                       \
   template void vec_copy<T>(T*, const T*, int64_t, hipStream_t);                                \
