@@ -190,6 +190,39 @@ hmg_status hmg_profile(hmg_ctx ctx, int32_t enable);
 hmg_status hmg_profile_read(hmg_ctx ctx, int32_t kernel, int64_t* launches, double* total_ms,
                             double* total_bytes);
 
+/* ---- batched cells (many independent cells, one launch per level-0 pass) --
+ * Not part of the paper's method: a throughput form for many small unit cells
+ * of uneven resolution.  The cells (each with its own multigrid hierarchy and
+ * six load cases) are solved in lockstep by FP32 MG-PCG: each level-0 pass
+ * (matvec, update, block Jacobi, residual, post-smoothing) is ONE persistent
+ * launch over the tiles of all cells (largest cells first), and each PCG
+ * iteration replays two captured HIP graphs that also hold the coarse levels
+ * and the scalar finalizers.  Convergence, residual recomputation and the
+ * per-case tolerance are those of hmg_solve_cases. */
+typedef struct hmg_batch_s* hmg_batch;
+
+/* base: material and solver settings (precision must be HMG_FP32; levels 0 =
+ * paper rule per cell); dims: ncells x (nx, ny, nz).  Every cell needs at
+ * least two multigrid levels.  hip_stream must be a created stream (graphs
+ * cannot be captured on the NULL stream); all batch calls run on it. */
+hmg_status hmg_batch_create(const hmg_config* base, int32_t ncells, const int32_t* dims,
+                            void* hip_stream, hmg_batch* out);
+hmg_status hmg_batch_destroy(hmg_batch b);
+/* rho_dev: float[nx*ny*nz] of that cell (as hmg_set_density). */
+hmg_status hmg_batch_set_density(hmg_batch b, int32_t cell, const float* rho_dev);
+/* Autotuner: times the batched matvec for candidate tile z-chunks (per cell
+ * size) and persistent grid sizes and keeps the fastest; grid_out (0 = one
+ * block per tile) and lz_out[ncells] (0 = default chunk) report the choice.
+ * Needs the densities set (it runs the real kernels). */
+hmg_status hmg_batch_tune(hmg_batch b, int32_t* grid_out, int32_t* lz_out);
+/* iters_out[ncells*6], relres_out[ncells*6] (recomputed FP64 relative
+ * residuals); HMG_E_NOT_CONVERGED if any case hit max_iter. */
+hmg_status hmg_batch_solve(hmg_batch b, double rel_tol, int32_t max_iter, int32_t* iters_out,
+                           double* relres_out);
+/* C_out[ncells*36]: each cell's homogenized tensor (as hmg_elastic_tensor). */
+hmg_status hmg_batch_elastic_tensors(hmg_batch b, double* C_out);
+const char* hmg_batch_last_error(hmg_batch b);
+
 /* ---- inspection entry points (used by the parity tests) ------------------ */
 
 /* Number of multigrid levels and the cells per axis of one level. */

@@ -11,6 +11,8 @@ SYMBOLS = (
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
     "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
     "hmg_load_vectors", "hmg_vcycle", "hmg_transfer", "hmg_profile", "hmg_profile_read",
+    "hmg_batch_create", "hmg_batch_destroy", "hmg_batch_set_density", "hmg_batch_tune",
+    "hmg_batch_solve", "hmg_batch_elastic_tensors", "hmg_batch_last_error",
     # include/hmg_nn.h
     "hmg_nn_create", "hmg_nn_destroy", "hmg_nn_param_count", "hmg_nn_get_params",
     "hmg_nn_set_params", "hmg_nn_get_grads", "hmg_nn_forward", "hmg_nn_backward",
@@ -73,6 +75,13 @@ def load() -> ctypes.CDLL:
         "hmg_transfer": ([vp, i32, i32, vp, vp], i32),
         "hmg_profile": ([vp, i32], i32),
         "hmg_profile_read": ([vp, i32, P(ctypes.c_int64), P(f64), P(f64)], i32),
+        "hmg_batch_create": ([P(HmgConfig), i32, P(i32), vp, P(vp)], i32),
+        "hmg_batch_destroy": ([vp], i32),
+        "hmg_batch_set_density": ([vp, i32, vp], i32),
+        "hmg_batch_tune": ([vp, P(i32), P(i32)], i32),
+        "hmg_batch_solve": ([vp, f64, i32, P(i32), P(f64)], i32),
+        "hmg_batch_elastic_tensors": ([vp, P(f64)], i32),
+        "hmg_batch_last_error": ([vp], ctypes.c_char_p),
         "hmg_nn_create": ([P(HmgNnConfig), vp, ctypes.c_uint64, P(vp)], i32),
         "hmg_nn_destroy": ([vp], i32),
         "hmg_nn_param_count": ([vp, P(i64)], i32),

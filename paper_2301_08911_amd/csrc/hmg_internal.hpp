@@ -128,6 +128,30 @@ void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, 
                         R* r, const double* scal, Partials part, int* nblk_out);
 int op0_blocks_per_case(const Grid& g);
 
+// Batched level-0 passes (FP32) over many cells in one persistent launch.
+// Vectors per kind:  matvec: in0 z, in1 p_old, out0 p_new, out1 q;
+// residual: in0 r, in1 z0, out0 t;  post-smooth: in0 z1, in1 r, in2 dinv,
+// in3 q (optional), out0 z.
+enum Op0BatchKind { OP0B_MATVEC = 0, OP0B_RESIDUAL = 1, OP0B_POST_SMOOTH = 2 };
+struct Op0BatchCell {
+  Grid g;
+  int lz;  // z-chunk of a tile (<= 0: default)
+  const float* s;
+  const float *in0, *in1, *in2, *in3;
+  float *out0, *out1;
+  const double* scal;
+  Partials part;
+};
+struct Op0BatchPlan;
+// Uploads the per-cell descriptors and the item list; `grid` blocks (<= 0: one
+// per item).  Returns nullptr if a device allocation fails.
+Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, int grid,
+                             hipStream_t st);
+void op0_batch_launch(const Op0BatchPlan* plan, const ModeK<float>& mk, hipStream_t st);
+void op0_batch_free(Op0BatchPlan* plan);
+int op0_batch_items(const Op0BatchPlan* plan);
+int op0_tiles_per_case(const Grid& g, int lz);
+
 // Macro-strain loads evaluated in FP64, stored as R; partial ||f||^2 in S_FF.
 template <typename R>
 void forcing(const Grid& g, const LoadTpl<double>& tpl, const double* s, R* f, Partials part,
@@ -150,6 +174,23 @@ void vec_update_r(const Grid& g, double* x, const V* p, T* r, const T* q, const 
                   Partials part, int* nblk_out, hipStream_t st);
 template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);
+// Batched FP32 pointwise passes over many cells (grid: nblk x cells):
+// update: x += alpha p, r -= alpha q (+ partials);  jacobi: z = Dinv (r - m),
+// m from the cell's scal.
+struct PwBatchCell {
+  Grid g;
+  double* x;
+  const float* p;
+  float* r;
+  const float* q;
+  const float* dinv;
+  float* z;
+  const double* scal;
+  Partials part;
+};
+void update_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st);
+void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st);
+int vec_blocks_for(int64_t n);
 // z = Dinv (r - m) with m from `mean` slots S_MEAN* (NULL: no shift).
 template <typename R, typename D, typename Z>
 void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,

@@ -13,7 +13,9 @@
 // that belongs to the next vertex plane in registers.  Lanes run along x, so
 // the x-neighbour part of the vertex gather is a cross-lane move (DPP); only
 // the y-neighbour part goes through LDS.
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "hmg_internal.hpp"
 
@@ -37,13 +39,16 @@ __host__ __device__ inline int modp(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-TileGeom tile_geom(const Grid& g) {
+TileGeom tile_geom(const Grid& g, int lz_req = 0) {
   TileGeom t;
   t.ntx = (g.nx + OX - 1) / OX;
   t.nty = (g.ny + OY - 1) / OY;
   const int base = t.ntx * t.nty * NCASE;
   int lz = g.nz;
-  while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 8192) lz = (lz + 1) / 2;
+  if (lz_req > 0)
+    lz = lz_req < g.nz ? lz_req : g.nz;
+  else
+    while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 8192) lz = (lz + 1) / 2;
   t.lz = lz;
   t.nzc = (g.nz + lz - 1) / lz;
   t.ntiles = t.ntx * t.nty * t.nzc;
@@ -192,14 +197,14 @@ struct Op0Waves {
   static constexpr int value = sizeof(T) == 4 ? HMG_OP0_WAVES : 2;
 };
 
+// One work item of a level-0 pass: case j % 6 of tile j / 6 of one cell.
 template <typename T, class Op>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
-op0_kernel(Op op_in, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) {
+__device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const TileGeom& tg,
+                                         const ModeK<T>& mk, const T* __restrict__ s, int j) {
   __shared__ T plane[2][3][PY][PX];
   __shared__ T rowc[2][3][TYE][TXE];
   __shared__ double red[NTHR / 64];
 
-  const int j = logical_block();
   const int c = j % NCASE;
   const int tile = j / NCASE;
   if (!op_in.active(c)) return;
@@ -385,6 +390,40 @@ op0_kernel(Op op_in, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) 
   if (Op::NACC > 1) {
     const double t1 = block_sum<NTHR / 64>(acc1, red);
     if (tid == 0) op.part.buf[(op.slot1 * 8 + c) * op.part.stride + tile] = t1;
+  }
+}
+
+template <typename T, class Op>
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
+op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) {
+  op0_body<T, Op>(op, g, tg, mk, s, logical_block());
+}
+
+// Batched form: one persistent grid works through the items of many cells.
+// Items are ordered cell by cell (largest cells first) and split into eight
+// contiguous ranges, one per XCD, so that the six cases of a tile and
+// neighbouring tiles still meet in one L2; the blocks of an XCD take the items
+// of its range round robin.
+template <typename T, class Op>
+struct Op0Cell {
+  Op op;
+  Grid g;
+  TileGeom tg;
+  const T* s;
+};
+
+template <typename T, class Op>
+__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
+op0_batched_kernel(const Op0Cell<T, Op>* __restrict__ cells, const int2* __restrict__ items,
+                   int nitems, ModeK<T> mk) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, per_xcd_blocks = (G + 7 - xcd) >> 3;  // blocks of this XCD
+  const int lo = (int)((int64_t)nitems * xcd / 8), hi = (int)((int64_t)nitems * (xcd + 1) / 8);
+  for (int it = lo + (b >> 3); it < hi; it += per_xcd_blocks) {
+    const int2 w = items[it];
+    const Op0Cell<T, Op>& ce = cells[w.x];
+    op0_body<T, Op>(ce.op, ce.g, ce.tg, mk, ce.s, w.y);
+    __syncthreads();  // the next item reuses the LDS buffers
   }
 }
 
@@ -803,6 +842,97 @@ inline int pw_blocks(int64_t n, int tpb, int cap) {
 }  // namespace
 
 int op0_blocks_per_case(const Grid& g) { return tile_geom(g).ntiles; }
+int op0_tiles_per_case(const Grid& g, int lz) { return tile_geom(g, lz).ntiles; }
+
+struct Op0BatchPlan {
+  int kind = 0;
+  void* cells = nullptr;
+  int2* items = nullptr;
+  int nitems = 0;
+  int grid = 0;
+};
+
+namespace {
+template <class Op>
+Op0BatchPlan* build_plan(int kind, const std::vector<Op0Cell<float, Op>>& hc, int grid,
+                         hipStream_t st) {
+  std::vector<int2> items;
+  for (int c = 0; c < (int)hc.size(); ++c)
+    for (int j = 0; j < hc[c].tg.ntiles * NCASE; ++j) items.push_back(make_int2(c, j));
+  Op0BatchPlan* p = new Op0BatchPlan;
+  p->kind = kind;
+  p->nitems = (int)items.size();
+  p->grid = grid > 0 ? std::min(grid, p->nitems) : p->nitems;
+  if (hipMalloc(&p->cells, sizeof(Op0Cell<float, Op>) * hc.size()) != hipSuccess ||
+      hipMalloc((void**)&p->items, sizeof(int2) * items.size()) != hipSuccess) {
+    op0_batch_free(p);
+    return nullptr;
+  }
+  (void)hipMemcpyAsync(p->cells, hc.data(), sizeof(Op0Cell<float, Op>) * hc.size(),
+                       hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(p->items, items.data(), sizeof(int2) * items.size(),
+                       hipMemcpyHostToDevice, st);
+  (void)hipStreamSynchronize(st);
+  return p;
+}
+}  // namespace
+
+Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, int grid,
+                             hipStream_t st) {
+  if (kind == OP0B_MATVEC) {
+    std::vector<Op0Cell<float, OpMatvecP<float, float>>> hc;
+    for (int c = 0; c < ncells; ++c) {
+      const Op0BatchCell& a = cells[c];
+      OpMatvecP<float, float> op{a.in0, a.in1, a.out0, a.out1, a.g.n, a.scal, a.part, S_PQ, 0,
+                                 0.f};
+      hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+    }
+    return build_plan(kind, hc, grid, st);
+  }
+  if (kind == OP0B_RESIDUAL) {
+    std::vector<Op0Cell<float, OpResidual<float, float>>> hc;
+    for (int c = 0; c < ncells; ++c) {
+      const Op0BatchCell& a = cells[c];
+      OpResidual<float, float> op{a.in0, a.in1, a.out0, a.g.n, a.scal, Partials{}, 0, 0, {}};
+      hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+    }
+    return build_plan(kind, hc, grid, st);
+  }
+  std::vector<Op0Cell<float, OpPostSmooth<float, float>>> hc;
+  for (int c = 0; c < ncells; ++c) {
+    const Op0BatchCell& a = cells[c];
+    OpPostSmooth<float, float> op{a.in0, a.in1, a.in2, a.out0, a.in3, a.g.n, a.scal, a.part,
+                                  S_RZNEW, S_QZ, {}};
+    hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+  }
+  return build_plan(kind, hc, grid, st);
+}
+
+void op0_batch_launch(const Op0BatchPlan* p, const ModeK<float>& mk, hipStream_t st) {
+  if (p->kind == OP0B_MATVEC)
+    hipLaunchKernelGGL((op0_batched_kernel<float, OpMatvecP<float, float>>), dim3(p->grid),
+                       dim3(NTHR), 0, st, (const Op0Cell<float, OpMatvecP<float, float>>*)p->cells,
+                       p->items, p->nitems, mk);
+  else if (p->kind == OP0B_RESIDUAL)
+    hipLaunchKernelGGL((op0_batched_kernel<float, OpResidual<float, float>>), dim3(p->grid),
+                       dim3(NTHR), 0, st,
+                       (const Op0Cell<float, OpResidual<float, float>>*)p->cells, p->items,
+                       p->nitems, mk);
+  else
+    hipLaunchKernelGGL((op0_batched_kernel<float, OpPostSmooth<float, float>>), dim3(p->grid),
+                       dim3(NTHR), 0, st,
+                       (const Op0Cell<float, OpPostSmooth<float, float>>*)p->cells, p->items,
+                       p->nitems, mk);
+}
+
+void op0_batch_free(Op0BatchPlan* p) {
+  if (!p) return;
+  if (p->cells) (void)hipFree(p->cells);
+  if (p->items) (void)hipFree(p->items);
+  delete p;
+}
+
+int op0_batch_items(const Op0BatchPlan* p) { return p->nitems; }
 
 template <typename T>
 void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal) {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -181,6 +182,8 @@ Status check_hip(const char* where) {
     if (_s.code != HMG_OK) return _s;        \
   } while (0)
 
+class BatchSolver;
+
 // T: arithmetic type of the solver vectors; V: their storage type (and that of
 // the coarse stencils).  The FP64 iterate, the FP64 scalars and the level-0
 // residual r (type T) are the same in every form.
@@ -189,12 +192,14 @@ class Solver final : public SolverIface {
   // Rounded storage makes the preconditioner vary slightly between
   // applications; beta then takes the Polak-Ribiere form.
   static constexpr bool kPR = !std::is_same<T, V>::value;
+  friend class BatchSolver;
 
  public:
   Solver(const hmg_config& cfg, hipStream_t st, const ElementConsts& ec, std::vector<Grid> grids)
       : cfg_(cfg), st_(st), ec_(ec), grids_(std::move(grids)) {}
 
   int levels() const override { return (int)grids_.size(); }
+  int stride_tiles(int lz) const { return op0_tiles_per_case(grids_[0], lz); }
   Grid level_grid(int l) const override { return grids_[l]; }
   double level_omega(int l) const override {
     return l < (int)omega_.size() ? omega_[l] : 0.0;
@@ -830,7 +835,386 @@ class Solver final : public SolverIface {
   double raw_relres_ = 0.0;     // warm start: relative residual before the correction cycle
 };
 
+
+// ---------------------------------------------------------------- batched cells
+// Many independent cells (each with its own hierarchy) solved in lockstep: one
+// PCG iteration is two captured graphs.  The level-0 passes (matvec, update,
+// Jacobi, residual, post-smoothing) are single launches over all cells (a
+// persistent grid over the cells' tiles, largest cells first); the coarse
+// levels and the scalar finalizers are per-cell launches inside the graphs.
+// The host reads the scalars of every cell once per iteration to decide
+// convergence and residual recomputations, exactly as in a single solve.
+class BatchSolver {
+ public:
+  using S = Solver<float, float, float>;
+  BatchSolver(hipStream_t st) : st_(st) {}
+  ~BatchSolver() {
+    free_plans();
+    for (auto* d : pw_) if (d) (void)hipFree(d);
+    if (hsc_) (void)hipHostFree(hsc_);
+  }
+
+  std::vector<std::unique_ptr<S>> cells;
+  std::vector<hmg_config> cfgs;
+  std::vector<int> lz;  // tuned z-chunk per cell (0 = default)
+  int grid = 0;         // persistent grid of the level-0 passes (0 = one block per item)
+
+  Status init() {
+    if (hipHostMalloc((void**)&hsc_, sizeof(double) * S_NSLOT * 8 * cells.size()) != hipSuccess)
+      return fail(HMG_E_OOM, "pinned host allocation failed");
+    lz.assign(cells.size(), 0);
+    // largest cells first: their tiles head the item list of every pass
+    order_.resize(cells.size());
+    for (size_t i = 0; i < cells.size(); ++i) order_[i] = (int)i;
+    std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) {
+      return cells[a]->grids_[0].n > cells[b]->grids_[0].n;
+    });
+    return Status{};
+  }
+
+  Status build_plans() {
+    free_plans();
+    const int B = (int)cells.size();
+    std::vector<Op0BatchCell> mv[2], rs, ps;
+    std::vector<PwBatchCell> up[2], jc;
+    nblk_ = 1;
+    for (int c : order_) nblk_ = std::max(nblk_, vec_blocks_for(cells[c]->grids_[0].n));
+    for (int c : order_) {
+      S& X = *cells[c];
+      const Grid& g = X.grids_[0];
+      if (op0_tiles_per_case(g, lz[c]) > X.stride_)
+        return fail(HMG_E_INVALID, "z-chunk %d gives more tiles than the partial buffers hold", lz[c]);
+      for (int par = 0; par < 2; ++par) {
+        float* pold = par ? X.pb_ : X.pa_;
+        float* pnew = par ? X.pa_ : X.pb_;
+        mv[par].push_back({g, lz[c], X.s_, X.z_, pold, nullptr, nullptr, pnew, X.q_, X.scal_,
+                           X.part_});
+        up[par].push_back({g, X.x_, pnew, X.r_, X.q_, nullptr, nullptr, X.scal_, X.part_});
+      }
+      rs.push_back({g, lz[c], X.s_, X.r_, X.w0_, nullptr, nullptr, X.t_, nullptr, X.scal_,
+                    Partials{}});
+      ps.push_back({g, lz[c], X.s_, X.w0_, X.r_, X.dinv0_, nullptr, X.z_, nullptr, X.scal_,
+                    X.part_});
+      jc.push_back({g, nullptr, nullptr, X.r_, nullptr, X.dinv0_, X.w0_, X.scal_, Partials{}});
+    }
+    for (int par = 0; par < 2; ++par) {
+      mvp_[par] = op0_batch_plan(OP0B_MATVEC, mv[par].data(), B, grid, st_);
+      if (!mvp_[par]) return fail(HMG_E_OOM, "batch plan allocation failed");
+    }
+    rsp_ = op0_batch_plan(OP0B_RESIDUAL, rs.data(), B, grid, st_);
+    psp_ = op0_batch_plan(OP0B_POST_SMOOTH, ps.data(), B, grid, st_);
+    if (!rsp_ || !psp_) return fail(HMG_E_OOM, "batch plan allocation failed");
+    auto upload = [&](const std::vector<PwBatchCell>& v, PwBatchCell** d) -> bool {
+      if (!*d && hipMalloc((void**)d, sizeof(PwBatchCell) * v.size()) != hipSuccess) return false;
+      (void)hipMemcpyAsync(*d, v.data(), sizeof(PwBatchCell) * v.size(), hipMemcpyHostToDevice,
+                           st_);
+      return true;
+    };
+    if (!upload(up[0], &pw_[0]) || !upload(up[1], &pw_[1]) || !upload(jc, &pw_[2]))
+      return fail(HMG_E_OOM, "batch descriptor allocation failed");
+    (void)hipStreamSynchronize(st_);
+    return check_hip("batch plans");
+  }
+
+  // Times the batched matvec for candidate z-chunks (per cell size) and
+  // persistent grid sizes; keeps the fastest.
+  Status tune(int* grid_out, int* lz_out) {
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    auto time_mv = [&]() -> double {
+      for (int w = 0; w < 2; ++w) launch_matvec(0);
+      (void)hipEventRecord(a, st_);
+      for (int k = 0; k < 5; ++k) launch_matvec(0);
+      (void)hipEventRecord(b, st_);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      return ms / 5.0;
+    };
+    for (auto& X : cells) scal_set_all_active(X->scal_, st_);
+    // z-chunk, one size class at a time (the others keep their current value)
+    std::vector<int> sizes;
+    for (auto& X : cells) sizes.push_back(X->grids_[0].nz);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    for (int nz : sizes) {
+      double best = 1e30;
+      int bestlz = 0;
+      for (int cand : {0, 4, 8, 16, 32, 64}) {
+        if (cand > nz) continue;
+        for (size_t c = 0; c < cells.size(); ++c)
+          if (cells[c]->grids_[0].nz == nz) lz[c] = cand;
+        Status st = build_plans();
+        if (st.code != HMG_OK) continue;
+        const double t = time_mv();
+        if (t < best) {
+          best = t;
+          bestlz = cand;
+        }
+      }
+      for (size_t c = 0; c < cells.size(); ++c)
+        if (cells[c]->grids_[0].nz == nz) lz[c] = bestlz;
+    }
+    double best = 1e30;
+    int bestg = 0;
+    for (int cand : {0, 512, 1024, 2048, 4096}) {
+      grid = cand;
+      HMG_TRY(build_plans());
+      const double t = time_mv();
+      if (t < best) {
+        best = t;
+        bestg = cand;
+      }
+    }
+    grid = bestg;
+    HMG_TRY(build_plans());
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *grid_out = grid;
+    for (size_t c = 0; c < cells.size(); ++c) lz_out[c] = lz[c];
+    tuned_ms_ = best;
+    return check_hip("batch tune");
+  }
+
+  Status solve(double tol, int max_iter, int* iters, double* relres) {
+    const int B = (int)cells.size();
+    for (auto& X : cells)
+      if (!X->have_density_) return fail(HMG_E_STATE, "a cell has no density");
+    if (!mvp_[0]) HMG_TRY(build_plans());
+    destroy_graphs();
+    std::vector<std::array<bool, NCASE>> active(B);
+    std::vector<std::array<int, NCASE>> count(B);
+    // per-cell start: x = 0, r = f, thresholds (as in a single solve)
+    for (int c = 0; c < B; ++c) {
+      S& X = *cells[c];
+      const Grid& g0 = X.grids_[0];
+      const int64_t F = (int64_t)NCASE * 3 * g0.n;
+      const double lam1 = X.cfg_.nu / ((1 + X.cfg_.nu) * (1 - 2 * X.cfg_.nu));
+      const double mu1 = 1.0 / (2 * (1 + X.cfg_.nu));
+      const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * X.mean_s_;
+      vec_fill<double>(X.x_, F, 0.0, st_);
+      vec_fill<float>(X.pa_, F, 0.f, st_);
+      scal_set_all_active(X.scal_, st_);
+      int nb = 0;
+      forcing<float>(g0, X.tpl64_, X.s64_, X.r_, X.part_, &nb, st_);
+      fin_sum(X.part_, S_FF, nb, X.scal_, true, st_);
+      (void)hipMemcpyAsync(X.scal_ + S_RR * 8, X.scal_ + S_FF * 8, sizeof(double) * 8,
+                           hipMemcpyDeviceToDevice, st_);
+      X.residual_mean(X.scal_);
+      fin_init(X.scal_, eps_abs, tol, st_);
+    }
+    HMG_TRY(read_all());
+    for (int c = 0; c < B; ++c) {
+      const double* h = hsc_ + (size_t)c * S_NSLOT * 8;
+      for (int k = 0; k < NCASE; ++k) {
+        active[c][k] = h[S_ACTIVE * 8 + k] != 0.0;
+        count[c][k] = 0;
+        cells[c]->last_true_[k] = std::sqrt(h[S_RR * 8 + k]);
+      }
+    }
+    vcycle();
+    for (int c = 0; c < B; ++c) {
+      S& X = *cells[c];
+      fin_sum(X.part_, S_RZNEW, X.stride_tiles(lz[c]), X.scal_, false, st_);
+      (void)hipMemcpyAsync(X.scal_ + S_RZ * 8, X.scal_ + S_RZNEW * 8, sizeof(double) * 8,
+                           hipMemcpyDeviceToDevice, st_);
+    }
+    auto any_active = [&]() {
+      for (int c = 0; c < B; ++c)
+        for (int k = 0; k < NCASE; ++k)
+          if (active[c][k]) return true;
+      return false;
+    };
+    int it = 0;
+    while (any_active() && it < max_iter) {
+      ++it;
+      HMG_TRY(run_graph(g1_[(it - 1) & 1], [&] { phase1((it - 1) & 1); }));
+      HMG_TRY(read_all());
+      for (int c = 0; c < B; ++c)
+        for (int k = 0; k < NCASE; ++k) count[c][k] += active[c][k] ? 1 : 0;
+      const bool replace = cfgs[0].replace_every > 0 && it % cfgs[0].replace_every == 0;
+      for (int c = 0; c < B; ++c) HMG_TRY(check_cell(c, replace, active[c]));
+      if (!any_active()) break;
+      HMG_TRY(run_graph(g2_, [&] { phase2(); }));
+    }
+    for (int c = 0; c < B; ++c) {
+      S& X = *cells[c];
+      const Grid& g0 = X.grids_[0];
+      int nb = 0;
+      Op0Launch<double> L64{g0, X.mk64_, X.s64_, st_};
+      vec_mean_partial<double>(g0, X.x_, X.part_, &nb, st_);
+      fin_mean(X.part_, nb, g0.n, X.aux_, st_);
+      vec_mean_subtract<double>(g0, X.x_, X.aux_, st_);
+      scal_set_all_active(X.aux_, st_);
+      op0_force_residual<float>(L64, X.tpl64_, X.x_, X.r_, X.aux_, X.part_, &nb);
+      fin_sum(X.part_, S_FF, nb, X.aux_, true, st_);
+      fin_sum(X.part_, S_TRUE, nb, X.aux_, true, st_);
+      HMG_TRY(X.read_scal(X.aux_, X.hscal_ + S_NSLOT * 8));
+      HMG_TRY(X.read_scal(X.scal_, X.hscal_));
+      const double* ha = X.hscal_ + S_NSLOT * 8;
+      for (int k = 0; k < NCASE; ++k) {
+        iters[c * NCASE + k] = count[c][k];
+        const bool trivial = X.hscal_[S_TRIVIAL * 8 + k] != 0.0;
+        const double ff = ha[S_FF * 8 + k];
+        relres[c * NCASE + k] = trivial || ff <= 0.0 ? 0.0 : std::sqrt(ha[S_TRUE * 8 + k] / ff);
+      }
+      X.have_solution_ = true;
+      X.have_iterate_ = true;
+    }
+    iters_run_ = it;
+    if (any_active())
+      return fail(HMG_E_NOT_CONVERGED, "max_iter %d reached before rel_tol %g", max_iter, tol);
+    return Status{};
+  }
+
+  double tuned_ms() const { return tuned_ms_; }
+
+ private:
+  void launch_matvec(int par) { op0_batch_launch(mvp_[par], cells[0]->mk_, st_); }
+
+  // matvec, alpha, update, residual norms and means (per parity of p)
+  void phase1(int par) {
+    launch_matvec(par);
+    for (size_t c = 0; c < cells.size(); ++c) {
+      S& X = *cells[c];
+      fin_sum(X.part_, S_PQ, X.stride_tiles(lz[c]), X.scal_, false, st_);
+      fin_alpha(X.scal_, st_);
+    }
+    update_batched(pw_[par], (int)cells.size(), nblk_, st_);
+    for (auto& X : cells) {
+      fin_sum(X->part_, S_RR, nblk_, X->scal_, false, st_);
+      fin_mean(X->part_, nblk_, X->grids_[0].n, X->scal_, st_);
+    }
+  }
+  // preconditioner and beta
+  void phase2() {
+    vcycle();
+    for (size_t c = 0; c < cells.size(); ++c) {
+      S& X = *cells[c];
+      fin_sum(X.part_, S_RZNEW, X.stride_tiles(lz[c]), X.scal_, false, st_);
+      fin_beta(X.scal_, false, st_);
+    }
+  }
+  void vcycle() {
+    jacobi0_batched(pw_[2], (int)cells.size(), nblk_, st_);
+    op0_batch_launch(rsp_, cells[0]->mk_, st_);
+    for (auto& Xp : cells) {
+      S& X = *Xp;
+      const Grid& g0 = X.grids_[0];
+      const int L = X.levels();
+      if (L == 1) continue;  // one-level cells are not batched (rejected at creation)
+      restrict_to<float>(g0, X.grids_[1], X.t_, X.lev_[1].r, X.scal_, st_);
+      X.descend(1, X.scal_);
+      if (L == 2)
+        prolong_add<float, float>(g0, X.grids_[1], X.w0_, X.zc_, X.scal_, false, st_);
+      else
+        prolong_add<float, float>(g0, X.grids_[1], X.w0_, X.lev_[1].z, X.scal_, false, st_);
+    }
+    op0_batch_launch(psp_, cells[0]->mk_, st_);
+  }
+
+  Status check_cell(int c, bool replace, std::array<bool, NCASE>& active) {
+    S& X = *cells[c];
+    const double* h = hsc_ + (size_t)c * S_NSLOT * 8;
+    bool check[NCASE], event[NCASE];
+    bool anycheck = false;
+    for (int k = 0; k < NCASE; ++k) {
+      const double rn = std::sqrt(h[S_RR * 8 + k]);
+      event[k] = active[k] && (rn <= h[S_THRESH * 8 + k] || rn <= 1e-2 * X.last_true_[k]);
+      check[k] = event[k] || (active[k] && replace);
+      anycheck |= check[k];
+    }
+    if (!anycheck) return Status{};
+    const Grid& g0 = X.grids_[0];
+    Op0Launch<double> L64{g0, X.mk64_, X.s64_, st_};
+    X.set_mask(X.aux_, check);
+    int nb = 0;
+    op0_force_residual<float>(L64, X.tpl64_, X.x_, X.r_, X.aux_, X.part_, &nb);
+    fin_sum(X.part_, S_TRUE, nb, X.aux_, false, st_);
+    HMG_TRY(X.read_scal(X.aux_, X.hscal_ + S_NSLOT * 8));
+    const double* ha = X.hscal_ + S_NSLOT * 8;
+    bool restart[NCASE], act[NCASE];
+    for (int k = 0; k < NCASE; ++k) {
+      restart[k] = false;
+      if (check[k]) {
+        const double tr = std::sqrt(ha[S_TRUE * 8 + k]);
+        X.last_true_[k] = tr;
+        if (tr <= h[S_THRESH * 8 + k])
+          active[k] = false;
+        else
+          restart[k] = event[k];
+      }
+      act[k] = active[k];
+    }
+    X.set_mask(X.scal_, act);
+    X.set_slot(X.scal_, S_RESTART, restart);
+    X.set_slot(X.scal_, S_REPLACED, check);
+    X.residual_mean(X.scal_);
+    return Status{};
+  }
+
+  template <class F>
+  Status run_graph(hipGraphExec_t& ex, F&& record) {
+    if (!ex) {
+      hipGraph_t gr = nullptr;
+      if (hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return check_hip("graph capture");
+      record();
+      if (hipStreamEndCapture(st_, &gr) != hipSuccess) return check_hip("graph capture end");
+      if (hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return check_hip("graph instantiate");
+      }
+      (void)hipGraphDestroy(gr);
+    }
+    if (hipGraphLaunch(ex, st_) != hipSuccess) return check_hip("graph launch");
+    return Status{};
+  }
+  void destroy_graphs() {
+    for (auto* e : {&g1_[0], &g1_[1], &g2_})
+      if (*e) {
+        (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+      }
+  }
+  void free_plans() {
+    destroy_graphs();
+    for (auto*& p : mvp_) {
+      op0_batch_free(p);
+      p = nullptr;
+    }
+    op0_batch_free(rsp_);
+    op0_batch_free(psp_);
+    rsp_ = psp_ = nullptr;
+  }
+  Status read_all() {
+    for (size_t c = 0; c < cells.size(); ++c)
+      (void)hipMemcpyAsync(hsc_ + c * S_NSLOT * 8, cells[c]->scal_, sizeof(double) * S_NSLOT * 8,
+                           hipMemcpyDeviceToHost, st_);
+    if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("batch scalar readback");
+    return check_hip("batch scalar readback");
+  }
+
+  hipStream_t st_;
+  std::vector<int> order_;
+  Op0BatchPlan* mvp_[2] = {nullptr, nullptr};
+  Op0BatchPlan *rsp_ = nullptr, *psp_ = nullptr;
+  PwBatchCell* pw_[3] = {nullptr, nullptr, nullptr};  // update (2 parities), Jacobi
+  hipGraphExec_t g1_[2] = {nullptr, nullptr};
+  hipGraphExec_t g2_ = nullptr;
+  double* hsc_ = nullptr;
+  int nblk_ = 1;
+  int iters_run_ = 0;
+  double tuned_ms_ = 0.0;
+};
+
 }  // namespace
+
+struct hmg_batch_s {
+  std::unique_ptr<BatchSolver> bs;
+  std::string err;
+};
 
 struct hmg_ctx_s {
   hmg_config cfg{};
@@ -1049,6 +1433,106 @@ hmg_status hmg_warm_start(hmg_ctx ctx, hmg_nn net, double accept_relres, double*
   *used_out = used;
   return report(ctx, s);
 }
+
+
+hmg_status hmg_batch_create(const hmg_config* base, int32_t ncells, const int32_t* dims,
+                            void* hip_stream, hmg_batch* out) {
+  if (!base || !dims || !out || ncells < 1 || ncells > 4096) return HMG_E_INVALID;
+  *out = nullptr;
+  if (!hip_stream) {
+    std::fprintf(stderr, "hmg_batch_create: graphs need a created stream, not the NULL stream\n");
+    return HMG_E_INVALID;
+  }
+  if (base->precision != HMG_FP32) {
+    std::fprintf(stderr, "hmg_batch_create: batched solves are FP32\n");
+    return HMG_E_INVALID;
+  }
+  ElementConsts* ec = new ElementConsts;
+  char err[256] = {0};
+  if (build_element_consts(base->nu, ec, err, sizeof(err)) != 0) {
+    std::fprintf(stderr, "hmg_batch_create: %s\n", err);
+    delete ec;
+    return HMG_E_INVALID;
+  }
+  hmg_batch b = new hmg_batch_s;
+  b->bs.reset(new BatchSolver((hipStream_t)hip_stream));
+  Status s;
+  for (int c = 0; c < ncells && s.code == HMG_OK; ++c) {
+    hmg_config cfg = *base;
+    cfg.nx = dims[3 * c];
+    cfg.ny = dims[3 * c + 1];
+    cfg.nz = dims[3 * c + 2];
+    std::vector<Grid> grids;
+    s = validate(cfg, &grids);
+    if (s.code == HMG_OK && grids.size() < 2)
+      s = fail(HMG_E_INVALID, "cell %d has a single multigrid level", c);
+    if (s.code != HMG_OK) break;
+    auto* X = new Solver<float, float, float>(cfg, (hipStream_t)hip_stream, *ec, grids);
+    b->bs->cells.emplace_back(X);
+    b->bs->cfgs.push_back(cfg);
+    s = X->init();
+  }
+  delete ec;
+  if (s.code == HMG_OK) s = b->bs->init();
+  if (s.code != HMG_OK) {
+    std::fprintf(stderr, "hmg_batch_create: %s\n", s.msg.c_str());
+    delete b;
+    return s.code;
+  }
+  *out = b;
+  return HMG_OK;
+}
+
+hmg_status hmg_batch_destroy(hmg_batch b) {
+  delete b;
+  return HMG_OK;
+}
+
+hmg_status hmg_batch_set_density(hmg_batch b, int32_t cell, const float* rho_dev) {
+  if (!b) return HMG_E_INVALID;
+  if (cell < 0 || cell >= (int)b->bs->cells.size() || !rho_dev) {
+    b->err = "bad cell index or NULL density";
+    return HMG_E_INVALID;
+  }
+  Status s = b->bs->cells[cell]->set_density(rho_dev);
+  b->err = s.msg;
+  return s.code;
+}
+
+hmg_status hmg_batch_tune(hmg_batch b, int32_t* grid_out, int32_t* lz_out) {
+  if (!b || !grid_out || !lz_out) return HMG_E_INVALID;
+  int g = 0;
+  std::vector<int> lz(b->bs->cells.size());
+  Status s = b->bs->tune(&g, lz.data());
+  *grid_out = g;
+  for (size_t c = 0; c < lz.size(); ++c) lz_out[c] = lz[c];
+  b->err = s.msg;
+  return s.code;
+}
+
+hmg_status hmg_batch_solve(hmg_batch b, double rel_tol, int32_t max_iter, int32_t* iters_out,
+                           double* relres_out) {
+  if (!b || !iters_out || !relres_out || !(rel_tol > 0.0) || max_iter <= 0) return HMG_E_INVALID;
+  std::vector<int> it(b->bs->cells.size() * NCASE);
+  Status s = b->bs->solve(rel_tol, max_iter, it.data(), relres_out);
+  for (size_t k = 0; k < it.size(); ++k) iters_out[k] = it[k];
+  b->err = s.msg;
+  return s.code;
+}
+
+hmg_status hmg_batch_elastic_tensors(hmg_batch b, double* C_out) {
+  if (!b || !C_out) return HMG_E_INVALID;
+  for (size_t c = 0; c < b->bs->cells.size(); ++c) {
+    Status s = b->bs->cells[c]->elastic(C_out + 36 * c);
+    if (s.code != HMG_OK) {
+      b->err = s.msg;
+      return s.code;
+    }
+  }
+  return HMG_OK;
+}
+
+const char* hmg_batch_last_error(hmg_batch b) { return b ? b->err.c_str() : "NULL batch"; }
 
 const char* hmg_last_error(hmg_ctx ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 

@@ -59,10 +59,10 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
 // r -= alpha q; partials of ||r||^2 and of sum(r) per case and component (the
 // translation component is removed before smoothing).
 template <typename T, typename V>
-__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
-                                                    const V* __restrict__ p, T* __restrict__ r,
-                                                    const T* __restrict__ q, const double* scal,
-                                                    Partials part) {
+__device__ __forceinline__ void update_body(const Grid& g, double* __restrict__ x,
+                                            const V* __restrict__ p, T* __restrict__ r,
+                                            const T* __restrict__ q, const double* scal,
+                                            const Partials& part) {
   __shared__ double red[(VB / 64) * NCASE * 4];
   bool on[NCASE];
   T al[NCASE];
@@ -104,11 +104,26 @@ __global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__
     }
 }
 
+template <typename T, typename V>
+__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
+                                                    const V* __restrict__ p, T* __restrict__ r,
+                                                    const T* __restrict__ q, const double* scal,
+                                                    Partials part) {
+  update_body<T, V>(g, x, p, r, q, scal, part);
+}
+
+// Batched forms: blockIdx.y selects the cell (its own grid-stride loop over
+// blockIdx.x), so one launch covers every cell of a batch.
+__global__ void __launch_bounds__(VB) update_batched_kernel(const PwBatchCell* __restrict__ cells) {
+  const PwBatchCell& ce = cells[blockIdx.y];
+  update_body<float, float>(ce.g, ce.x, ce.p, ce.r, ce.q, ce.scal, ce.part);
+}
+
 // z = Dinv (r - m), m the per-component mean in `mean` (slots S_MEAN*, may be NULL).
 template <typename R, typename D, typename Z>
-__global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const R* __restrict__ r,
-                                                     const D* __restrict__ dinv, Z* __restrict__ z,
-                                                     const double* scal, const double* mean) {
+__device__ __forceinline__ void jacobi0_body(const Grid& g, const R* __restrict__ r,
+                                             const D* __restrict__ dinv, Z* __restrict__ z,
+                                             const double* scal, const double* mean) {
   using A = typename Acc<Z>::type;
   bool on[NCASE];
 #pragma unroll
@@ -135,6 +150,18 @@ __global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const R* __restrict
       z[(int64_t)(c * 3 + 2) * n + i] = (Z)(dxz * r0 + dyz * r1 + dzz * r2);
     }
   }
+}
+
+template <typename R, typename D, typename Z>
+__global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const R* __restrict__ r,
+                                                     const D* __restrict__ dinv, Z* __restrict__ z,
+                                                     const double* scal, const double* mean) {
+  jacobi0_body<R, D, Z>(g, r, dinv, z, scal, mean);
+}
+
+__global__ void __launch_bounds__(VB) jacobi0_batched_kernel(const PwBatchCell* __restrict__ cells) {
+  const PwBatchCell& ce = cells[blockIdx.y];
+  jacobi0_body<float, float, float>(ce.g, ce.r, ce.dinv, ce.z, ce.scal, ce.scal);
 }
 
 template <typename T>
@@ -367,6 +394,14 @@ inline int blocks_for(int64_t n) {
 }  // namespace
 
 int vec_blocks(const Grid& g) { return blocks_for(g.n); }
+
+void update_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(update_batched_kernel, dim3(nblk, ncells), dim3(VB), 0, st, cells_dev);
+}
+void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(jacobi0_batched_kernel, dim3(nblk, ncells), dim3(VB), 0, st, cells_dev);
+}
+int vec_blocks_for(int64_t n) { return blocks_for(n); }
 
 template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st) {

@@ -209,3 +209,66 @@ class Context:
                                           _ptr(self._field(inp, nin, "in")),
                                           _ptr(self._field(out, nout, "out"))))
         return out
+
+
+class Batch:
+    """Many cells solved in lockstep (hmg_batch_create ... hmg_batch_destroy)."""
+
+    def __init__(self, shapes, *, E0=1.0, nu=0.3, penal=3.0, Emin=1e-9, replace_every=0,
+                 stream: torch.cuda.Stream | None = None):
+        self.lib = _lib.load()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        # graphs cannot be captured on the legacy default stream: own a stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        cfg = _lib.HmgConfig(0, 0, 0, E0, nu, penal, Emin, 0, 0.0, 1, 1, PRECISIONS["fp32"],
+                             replace_every)
+        dims = (ctypes.c_int32 * (3 * len(self.shapes)))(*[v for s in self.shapes for v in s])
+        h = ctypes.c_void_p()
+        st = self.lib.hmg_batch_create(ctypes.byref(cfg), len(self.shapes), dims,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise HmgError(st, "hmg_batch_create failed (see stderr)")
+        self._h = h
+
+    def _check(self, st, allow=(OK,)):
+        if st not in allow:
+            raise HmgError(st, self.lib.hmg_batch_last_error(self._h).decode())
+        return st
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.hmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_density(self, cell: int, rho: torch.Tensor):
+        nx, ny, nz = self.shapes[cell]
+        if rho.dtype != torch.float32 or not rho.is_contiguous() or rho.numel() != nx * ny * nz:
+            raise ValueError("rho must be a contiguous float32 tensor of the cell's size")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self._check(self.lib.hmg_batch_set_density(self._h, cell, _ptr(rho)))
+
+    def tune(self):
+        g = ctypes.c_int32()
+        lz = (ctypes.c_int32 * len(self.shapes))()
+        self._check(self.lib.hmg_batch_tune(self._h, ctypes.byref(g), lz))
+        return g.value, list(lz)
+
+    def solve(self, rel_tol: float, max_iter: int) -> SolveResult:
+        B = len(self.shapes)
+        it = (ctypes.c_int32 * (6 * B))()
+        rr = (ctypes.c_double * (6 * B))()
+        st = self._check(self.lib.hmg_batch_solve(self._h, rel_tol, max_iter, it, rr),
+                         allow=(OK, E_NOT_CONVERGED))
+        return SolveResult(np.array(it[:]).reshape(B, 6), np.array(rr[:]).reshape(B, 6), st == OK)
+
+    def elastic_tensors(self) -> np.ndarray:
+        B = len(self.shapes)
+        C = (ctypes.c_double * (36 * B))()
+        self._check(self.lib.hmg_batch_elastic_tensors(self._h, C))
+        return np.array(C[:]).reshape(B, 6, 6)
