@@ -3,25 +3,31 @@
 
 One step = one optimization iteration of the hot path on a resident cell:
 density filter -> SIMP scale + multigrid hierarchy -> MG-PCG solve of the six
-load cases (warm-started from the previous iterate) -> C^H -> bulk-modulus
-sensitivities -> filter adjoint -> OC update.
+load cases -> C^H -> bulk-modulus sensitivities -> filter adjoint -> OC update.
 
 Workload (default): 512^3 periodic cell, seeded Gaussian-smoothed noise
 (sigma = 3*512/64 = 24 voxels) thresholded to volume fraction 0.3 with a 1e-3
 floor, E0 = 1, nu = 0.3, p = 3, Emin = 1e-9, FP32 MG-PCG to relative residual
-1e-6 (FP64 dot products, iterate and residual recomputation).
+1e-6 (FP64 dot products, iterate and residual recomputation), each solve
+started from the previous optimization iterate.
 
 Prints one JSON line.  value = MG-PCG DOF-iterations per second over the timed
-solves (3 n DOFs per case x PCG iterations of each case / solve wall time);
-s_per_opt_iter is reported beside it.  The roofline object covers the level-0
-kernel with the largest share of the timed solve time, timed with HIP events
-on the context stream; the CPU baseline times the FP64 oracle on a bounded
-sample (a box-downsampled copy of the same cell, a fixed number of PCG
-iterations).
+solves of the first form (3 n DOFs per case x PCG iterations of each case /
+solve wall time); s_per_opt_iter is reported beside it.  --forms adds the
+other forms of the method on the same cell (each gets its own warm-up and
+steps): mixed_bf16 (bf16 multigrid vectors), learned (network warm start with
+the cold start as fallback), cold (zero start every step).  The roofline object
+covers the level-0 kernel with the largest share of the timed solve time of the
+first form, timed with HIP events on the context stream; its HBM traffic comes
+from the committed rocprofv3 counter summary when that summary was taken on the
+same kernel source.  The CPU baseline times the FP64 oracle on a bounded
+sample.  --workload batch48 runs the batched form instead: 48 cells with sizes
+drawn from {32, 48, 64, 96, 128}^3 in lockstep.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,10 +37,53 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_level0_512cube.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_08911_amd", "csrc", f)
+                  for f in ("level0.hip", "vector.hip", "hmg_internal.hpp")]
 
 
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(paths=KERNEL_SOURCES):
+    """Short digest of the level-0 kernel sources (ties counter data to a build)."""
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current level-0 source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256_16") != source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+
+
+def copy_bandwidth(nbytes=1 << 31, reps=5):
+    """Device-to-device copy rate (read + write bytes / time), HIP events."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(rho_full, n_full: int, sample: int, iters: int) -> dict:
@@ -65,49 +114,36 @@ def cpu_baseline(rho_full, n_full: int, sample: int, iters: int) -> dict:
                       f"iterations x 6 cases in FP64 (scipy CSR, one thread); {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=512, help="cells per axis")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--max-iter", type=int, default=2000)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU sharding is design-only)", file=sys.stderr)
-        sys.exit(2)
-
+def run_form(form, x0_host, n, args, W, profile):
+    """Warm-up and timed optimization steps of one form; returns its record."""
     import numpy as np
     import torch
     from oracle import hmgref as O
-    from paper_2301_08911_amd import inputs as I
     from paper_2301_08911_amd.hmg import Context
-
-    torch.cuda.set_device(0)
-    n = args.n
     shape = (n, n, n)
-    sigma = 3.0 * n / 64.0
-    log(f"generating {n}^3 smoothed-noise cell (sigma {sigma:g}, VF 0.3)")
-    t = time.perf_counter()
-    x_host = I.smoothed_noise_density(shape, args.seed, 0.3, sigma=sigma)
-    log(f"  done in {time.perf_counter() - t:.1f} s")
-    x = torch.from_numpy(x_host.astype(np.float32).ravel()).cuda()
-    rho = torch.empty_like(x)
-    g = torch.empty_like(x)
-    gx = torch.empty_like(x)
-    W = O.bulk_weights()
-    ctx = Context(shape, precision=args.precision, Emin=1e-9)
-    log(f"context: {ctx.num_levels()} levels, omega {[round(ctx.level_omega(l), 3) for l in range(ctx.num_levels())]}")
+    prec = "mixed_bf16" if form == "mixed_bf16" else "fp32"
+    x = torch.from_numpy(x0_host.astype(np.float32).ravel()).cuda()
+    rho, g, gx = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    ctx = Context(shape, precision=prec, Emin=1e-9)
+    net = None
+    if form == "learned":
+        from paper_2301_08911_amd import nn
+        net = nn.Net()
+        net.load(os.path.join(ROOT, "paper_2301_08911_amd", "weights", "warmstart_l4c8.npy"))
+    guesses = []
 
-    def opt_step(init):
+    def opt_step(first):
         ctx.filter(x, out=rho, radius=2.0)
         ctx.set_density(rho)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
+        if form == "learned":
+            from paper_2301_08911_amd import nn
+            rr, used = nn.warm_start(ctx, net, 0.5)
+            guesses.append((round(rr, 4), used))
+            init = 1
+        else:
+            init = 0 if (first or form == "cold") else 1
         res = ctx.solve_cases(args.tol, args.max_iter, init=init)
         ts = time.perf_counter() - t0
         C = ctx.elastic_tensor()
@@ -117,68 +153,171 @@ def main():
         return res, ts, C
 
     for w in range(args.warmup):
-        res, ts, C = opt_step(0 if w == 0 else 1)
-        log(f"warmup {w}: iters {res.iters.tolist()} relres max {res.relres.max():.2e} solve {ts:.3f} s "
-            f"B {O.bulk_modulus(C):.5f}")
+        res, ts, C = opt_step(w == 0)
+        log(f"{form} warmup {w}: iters {res.iters.tolist()} solve {ts:.3f} s B {O.bulk_modulus(C):.6f}")
     torch.cuda.synchronize()
-    ctx.profile(True)
-    total_dofit = 0.0
-    solve_s = 0.0
-    iters_all = []
-    relres_max = 0.0
+    if profile:
+        ctx.profile(True)
+    total_dofit, solve_s, iters_all, relres_max, Bs = 0.0, 0.0, [], 0.0, []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        res, ts, C = opt_step(0 if (args.warmup == 0 and k == 0) else 1)
+        res, ts, C = opt_step(args.warmup == 0 and k == 0)
         total_dofit += float(res.iters.sum()) * 3 * ctx.n
         solve_s += ts
         iters_all.append(res.iters.tolist())
         relres_max = max(relres_max, float(res.relres.max()))
-        log(f"step {k}: iters {res.iters.tolist()} relres max {res.relres.max():.2e} solve {ts:.3f} s "
-            f"B {O.bulk_modulus(C):.5f} converged {res.converged}")
+        Bs.append(O.bulk_modulus(C))
+        log(f"{form} step {k}: iters {res.iters.tolist()} relres max {res.relres.max():.2e} "
+            f"solve {ts:.3f} s B {Bs[-1]:.6f} converged {res.converged}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    rec = {"dof_iters_per_s": total_dofit / solve_s if solve_s > 0 else 0.0,
+           "s_per_opt_iter": elapsed / args.steps, "solve_s_per_opt_iter": solve_s / args.steps,
+           "pcg_iters": iters_all, "max_relres": relres_max, "bulk_modulus": Bs,
+           "precision": prec}
+    if guesses:
+        rec["warm_start_relres_used"] = guesses
+    prof = ctx.profile_read() if profile else None
+    if profile:
+        ctx.profile(False)
+    levels = ctx.num_levels()
+    ctx.destroy()
+    return rec, prof, levels
 
-    # dominant level-0 kernel of the timed solves
+
+def bench_batch(args):
+    """48 cells of sizes drawn from {32, 48, 64, 96, 128}^3, solved in lockstep."""
+    import numpy as np
+    import torch
+    from paper_2301_08911_amd import inputs as I
+    from paper_2301_08911_amd.hmg import Batch
+    sizes = (32, 48, 64, 96, 128)
+    pick = I.uniform01(args.seed, 11, 48)
+    shapes = [(sizes[int(u * 5)],) * 3 for u in pick]
+    vfs = 0.1 + 0.4 * I.uniform01(args.seed, 12, 48)
+    torch.cuda.set_device(0)
+    b = Batch(shapes)
+    t = time.perf_counter()
+    for k, (s, vf) in enumerate(zip(shapes, vfs)):
+        rho = I.smoothed_noise_density(s, args.seed * 100 + k, float(vf), sigma=3.0)
+        b.set_density(k, torch.from_numpy(rho.astype(np.float32).ravel()).cuda())
+    torch.cuda.synchronize()
+    log(f"batch: {len(shapes)} cells, {sum(np.prod(s) for s in shapes)} vertices, "
+        f"densities in {time.perf_counter() - t:.1f} s")
+    grid, lz = b.tune()
+    log(f"autotuned grid {grid}, z-chunk per cell {lz}")
+    for w in range(args.warmup):
+        r = b.solve(args.tol, args.max_iter)
+        log(f"warmup {w}: max iters {r.iters.max()}")
+    times, dofit = [], 0.0
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = b.solve(args.tol, args.max_iter)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        dofit += float(sum(r.iters[c].sum() * 3 * np.prod(shapes[c]) for c in range(len(shapes))))
+        log(f"step {k}: {times[-1]:.3f} s, max iters {r.iters.max()}, max relres {r.relres.max():.2e}")
+    total = sum(times)
+    return {
+        "metric": "MG-PCG DOF-iters/s, 48 batched cells (sizes 32-128)",
+        "value": dofit / total, "unit": "DOF-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "48 periodic cells, sizes from {32,48,64,96,128}^3, smoothed noise "
+                               "sigma 3, VF U[0.1,0.5], FP32 MG-PCG to 1e-6, cold start, one "
+                               "persistent launch per level-0 pass, captured graphs",
+                   "cells": [list(s) for s in shapes], "tuned_grid": grid, "tuned_lz": lz},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="cells per axis")
+    ap.add_argument("--forms", default="plain",
+                    help="comma list of plain, mixed_bf16, learned, cold (first = headline)")
+    ap.add_argument("--workload", default="cell", choices=["cell", "batch48"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (multi-GPU "
+              "sharding is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batch48":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+
+    import numpy as np
+    import torch
+    from oracle import hmgref as O
+    from paper_2301_08911_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    n = args.n
+    sigma = 3.0 * n / 64.0
+    log(f"generating {n}^3 smoothed-noise cell (sigma {sigma:g}, VF 0.3)")
+    t = time.perf_counter()
+    x_host = I.smoothed_noise_density((n, n, n), args.seed, 0.3, sigma=sigma)
+    log(f"  done in {time.perf_counter() - t:.1f} s")
+    W = O.bulk_weights()
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    records, prof, levels = {}, None, 0
+    for i, form in enumerate(forms):
+        rec, p, L = run_form(form, x_host, n, args, W, profile=(i == 0))
+        records[form] = rec
+        if i == 0:
+            prof, levels = p, L
+    head = records[forms[0]]
+
+    # dominant level-0 kernel of the timed solves of the headline form
     name, (cnt, ms, by) = max(((k, v) for k, v in prof.items() if v[0] > 0),
                               key=lambda kv: kv[1][1])
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    traffic = measured_traffic(name)
     kernel_table = {k: {"launches": v[0], "ms": round(v[1], 3),
                         "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                     for k, v in prof.items()}
-    value = total_dofit / solve_s if solve_s > 0 else 0.0
     out = {
         "metric": "MG-PCG DOF-iters/s + s per opt-iter at 512^3 (learned/mixed vs plain)",
-        "value": value,
+        "value": head["dof_iters_per_s"],
         "unit": "DOF-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "s_per_opt_iter": elapsed / args.steps,
-        "solve_s_per_opt_iter": solve_s / args.steps,
-        "pcg_iters": iters_all,
-        "max_relres": relres_max,
+        "ms_per_step": head["s_per_opt_iter"] * 1e3,
+        "s_per_opt_iter": head["s_per_opt_iter"],
+        "solve_s_per_opt_iter": head["solve_s_per_opt_iter"],
+        "pcg_iters": head["pcg_iters"],
+        "max_relres": head["max_relres"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{n}^3 periodic cell, smoothed noise sigma {sigma:g} VF 0.3, "
-                               f"bulk objective, {args.precision.upper()} MG-PCG to {args.tol:g}, "
-                               "warm start from the previous iterate, filter radius 2, OC",
-                   "cells": n ** 3, "levels": ctx.num_levels(), "precision": args.precision},
+                               f"bulk objective, {forms[0]} FP32 MG-PCG to {args.tol:g}, "
+                               "filter radius 2, OC",
+                   "cells": n ** 3, "levels": levels, "form": forms[0]},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": cnt, "avg_ms": ms / cnt if cnt else None,
-                     "algorithmic_bytes_per_launch": by / cnt if cnt else None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "launches": cnt, "avg_ms": ms / cnt if cnt else None,
+                     "algorithmic_bytes_per_launch": by / cnt if cnt else None,
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "kernels": kernel_table,
+        "forms": records,
     }
     if not args.no_cpu_baseline:
-        sample = 32 if n >= 32 else n
         log("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(x_host, n, sample, 120)
+        out["cpu_baseline"] = cpu_baseline(x_host, n, 32 if n >= 32 else n, 120)
     print(json.dumps(out), flush=True)
 
 
