@@ -39,8 +39,34 @@ __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
 
+// Two consecutive values of a row (the even one first): one aligned load or
+// store of 2 * sizeof(T) bytes.  Rows start at even offsets (every grid that
+// is coarsened has even extents), so 2X is always pair-aligned.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T v[2];
+};
+
+// Row r of a launch over `rows` rows: consecutive block indices go to
+// different XCDs, so hand each XCD a contiguous range of rows (neighbouring
+// rows share their coarse or fine partner rows in that XCD's L2).
+__device__ __forceinline__ int xcd_row(int rows) {
+  const int b = blockIdx.x;
+  if (rows % 8 != 0) return b;
+  return (b & 7) * (rows >> 3) + (b >> 3);
+}
+
+inline int row_threads(int nx) { return nx >= 256 ? 256 : (nx > 64 ? 128 : 64); }
+
 // MODE 0: out = K u.  MODE 1: out = (r - m) - K u.  MODE 2: out = u + Dinv ((r - m) - K u).
 // m is the per-component mean of r (slots S_MEAN* of `mean`, FP64).
+//
+// One block per grid row (y, z), a thread per x.  The 27 neighbour offsets
+// are 32-bit (a level holds fewer than 2^31 vertices) on top of uniform
+// component base pointers.  Every case is computed whether active or not, so
+// that no load waits behind a branch; the sums of an inactive case depend on
+// its own (stale) buffers only and are never stored.  The stencil stream, read
+// once for all six cases, dominates the traffic either way.
 template <typename T, typename W, int MODE>
 __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u,
                                const T* __restrict__ r, const W* __restrict__ dinv,
@@ -49,142 +75,166 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
-  const int64_t n = g.n;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int gx = (int)(i % g.nx);
-    const int gy = (int)((i / g.nx) % g.ny);
-    const int gz = (int)(i / ((int64_t)g.nx * g.ny));
-    int xs[3] = {gx == 0 ? g.nx - 1 : gx - 1, gx, gx + 1 == g.nx ? 0 : gx + 1};
-    int ys[3] = {gy == 0 ? g.ny - 1 : gy - 1, gy, gy + 1 == g.ny ? 0 : gy + 1};
-    int zs[3] = {gz == 0 ? g.nz - 1 : gz - 1, gz, gz + 1 == g.nz ? 0 : gz + 1};
+  const int n = (int)g.n;
+  const int row = xcd_row(g.ny * g.nz);
+  const int gy = row % g.ny, gz = row / g.ny;
+  for (int gx = threadIdx.x; gx < g.nx; gx += blockDim.x) {
+    const int i = row * g.nx + gx;
     A acc[NCASE][3];
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
-    for (int d = 0; d < 27; ++d) {
-      const int dx = d % 3, dy = (d / 3) % 3, dz = d / 9;
-      const int64_t w = xs[dx] + (int64_t)g.nx * (ys[dy] + (int64_t)g.ny * zs[dz]);
-      A K[9];
+    // neighbour rows (dy, dz), then the three x offsets of each row
+    for (int a = 0; a < 9; ++a) {
+      int y = gy + a % 3 - 1, z = gz + a / 3 - 1;
+      y = y < 0 ? y + g.ny : (y == g.ny ? 0 : y);
+      z = z < 0 ? z + g.nz : (z == g.nz ? 0 : z);
+      const int rb = g.nx * (y + g.ny * z);
 #pragma unroll
-      for (int t = 0; t < 9; ++t) K[t] = (A)st[(int64_t)(d * 9 + t) * n + i];
+      for (int dx = 0; dx < 3; ++dx) {
+        int x = gx + dx - 1;
+        x = x < 0 ? x + g.nx : (x == g.nx ? 0 : x);
+        const int w = rb + x;
+        const W* sd = st + (size_t)((3 * a + dx) * 9) * n;
+        A K[9];
 #pragma unroll
-      for (int c = 0; c < NCASE; ++c) {
-        if (!on[c]) continue;
-        const A u0 = (A)u[(int64_t)(c * 3 + 0) * n + w];
-        const A u1 = (A)u[(int64_t)(c * 3 + 1) * n + w];
-        const A u2 = (A)u[(int64_t)(c * 3 + 2) * n + w];
-        acc[c][0] += K[0] * u0 + K[1] * u1 + K[2] * u2;
-        acc[c][1] += K[3] * u0 + K[4] * u1 + K[5] * u2;
-        acc[c][2] += K[6] * u0 + K[7] * u1 + K[8] * u2;
+        for (int t = 0; t < 9; ++t) K[t] = (A)(sd + (size_t)t * n)[i];
+#pragma unroll
+        for (int c = 0; c < NCASE; ++c) {
+          const A u0 = (A)(u + (size_t)(c * 3 + 0) * n)[w];
+          const A u1 = (A)(u + (size_t)(c * 3 + 1) * n)[w];
+          const A u2 = (A)(u + (size_t)(c * 3 + 2) * n)[w];
+          acc[c][0] += K[0] * u0 + K[1] * u1 + K[2] * u2;
+          acc[c][1] += K[3] * u0 + K[4] * u1 + K[5] * u2;
+          acc[c][2] += K[6] * u0 + K[7] * u1 + K[8] * u2;
+        }
       }
     }
     A D[6];
     if (MODE == 2) {
 #pragma unroll
-      for (int t = 0; t < 6; ++t) D[t] = (A)dinv[(int64_t)t * n + i];
+      for (int t = 0; t < 6; ++t) D[t] = (A)(dinv + (size_t)t * n)[i];
     }
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
       if (MODE == 0) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = (T)acc[c][k];
+        for (int k = 0; k < 3; ++k) (out + (size_t)(c * 3 + k) * n)[i] = (T)acc[c][k];
       } else {
         A res[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          res[k] = (A)(to_d(r[(int64_t)(c * 3 + k) * n + i]) - mean[(S_MEAN0 + k) * 8 + c]) -
+          res[k] = (A)(to_d((r + (size_t)(c * 3 + k) * n)[i]) - mean[(S_MEAN0 + k) * 8 + c]) -
                    acc[c][k];
         if (MODE == 1) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) out[(int64_t)(c * 3 + k) * n + i] = (T)res[k];
+          for (int k = 0; k < 3; ++k) (out + (size_t)(c * 3 + k) * n)[i] = (T)res[k];
         } else {
-          const A z0 = (A)u[(int64_t)(c * 3 + 0) * n + i] + (D[0] * res[0] + D[3] * res[1] + D[5] * res[2]);
-          const A z1 = (A)u[(int64_t)(c * 3 + 1) * n + i] + (D[3] * res[0] + D[1] * res[1] + D[4] * res[2]);
-          const A z2 = (A)u[(int64_t)(c * 3 + 2) * n + i] + (D[5] * res[0] + D[4] * res[1] + D[2] * res[2]);
-          out[(int64_t)(c * 3 + 0) * n + i] = (T)z0;
-          out[(int64_t)(c * 3 + 1) * n + i] = (T)z1;
-          out[(int64_t)(c * 3 + 2) * n + i] = (T)z2;
+          const A z0 = (A)(u + (size_t)(c * 3 + 0) * n)[i] + (D[0] * res[0] + D[3] * res[1] + D[5] * res[2]);
+          const A z1 = (A)(u + (size_t)(c * 3 + 1) * n)[i] + (D[3] * res[0] + D[1] * res[1] + D[4] * res[2]);
+          const A z2 = (A)(u + (size_t)(c * 3 + 2) * n)[i] + (D[5] * res[0] + D[4] * res[1] + D[2] * res[2]);
+          (out + (size_t)(c * 3 + 0) * n)[i] = (T)z0;
+          (out + (size_t)(c * 3 + 1) * n)[i] = (T)z1;
+          (out + (size_t)(c * 3 + 2) * n)[i] = (T)z2;
         }
       }
     }
   }
 }
 
-// rc[V] = sum_{a in {-1,0,1}^3} w(a) tf[2V + a], w(a) = prod (a_k == 0 ? 1 : 1/2)
+// Restriction R = P^T (unscaled weights, Sec. 3.3):
+//   rc[V] = sum_{a in {-1,0,1}^3} w(a) tf[2V + a],  w(a) = prod_k (a_k == 0 ? 1 : 1/2).
+// One block per coarse row (Y, Z); a thread per coarse X reads the pair
+// (2X, 2X+1) and the value 2X-1 of each of the 9 fine rows 2Y+{-1,0,1} x
+// 2Z+{-1,0,1}.
 template <typename T>
 __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* __restrict__ rc,
                                 const double* scal) {
+  using A = typename Acc<T>::type;
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
-  using A = typename Acc<T>::type;
-  for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < gc.n;
-       I += (int64_t)gridDim.x * blockDim.x) {
-    const int X = (int)(I % gc.nx);
-    const int Y = (int)((I / gc.nx) % gc.ny);
-    const int Z = (int)(I / ((int64_t)gc.nx * gc.ny));
-    int xs[3] = {modp(2 * X - 1, gf.nx), 2 * X, 2 * X + 1};
-    int ys[3] = {modp(2 * Y - 1, gf.ny), 2 * Y, 2 * Y + 1};
-    int zs[3] = {modp(2 * Z - 1, gf.nz), 2 * Z, 2 * Z + 1};
-    A acc[NCASE][3];
+  const int row = xcd_row(gc.ny * gc.nz);
+  const int Y = row % gc.ny, Z = row / gc.ny;
+  const int ys[3] = {Y == 0 ? gf.ny - 1 : 2 * Y - 1, 2 * Y, 2 * Y + 1};
+  const int zs[3] = {Z == 0 ? gf.nz - 1 : 2 * Z - 1, 2 * Z, 2 * Z + 1};
+  int64_t fb[9];
 #pragma unroll
-    for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
-    for (int a = 0; a < 27; ++a) {
-      const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-      const A w = A((ax == 1 ? 1.0 : 0.5) * (ay == 1 ? 1.0 : 0.5) * (az == 1 ? 1.0 : 0.5));
-      const int64_t f = xs[ax] + (int64_t)gf.nx * (ys[ay] + (int64_t)gf.ny * zs[az]);
-#pragma unroll
-      for (int c = 0; c < NCASE; ++c) {
-        if (!on[c]) continue;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) acc[c][k] += w * (A)tf[(int64_t)(c * 3 + k) * gf.n + f];
-      }
-    }
+  for (int a = 0; a < 9; ++a) fb[a] = (int64_t)gf.nx * (ys[a % 3] + (int64_t)gf.ny * zs[a / 3]);
+  const int64_t cb = (int64_t)row * gc.nx;
+  for (int X = threadIdx.x; X < gc.nx; X += blockDim.x) {
+    const int xm = X == 0 ? gf.nx - 1 : 2 * X - 1;
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) rc[(int64_t)(c * 3 + k) * gc.n + I] = (T)acc[c][k];
+      for (int k = 0; k < 3; ++k) {
+        const T* f = tf + (int64_t)(c * 3 + k) * gf.n;
+        A rowsum[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          const Pair<T> p = *reinterpret_cast<const Pair<T>*>(f + fb[a] + 2 * X);
+          rowsum[a] = (A)p.v[0] + A(0.5) * ((A)p.v[1] + (A)f[fb[a] + xm]);
+        }
+        // weights 1/2, 1, 1/2 along y, then along z
+        A s = A(0);
+#pragma unroll
+        for (int az = 0; az < 3; ++az) {
+          const A sy = rowsum[3 * az + 1] + A(0.5) * (rowsum[3 * az] + rowsum[3 * az + 2]);
+          s += (az == 1 ? A(1) : A(0.5)) * sy;
+        }
+        rc[(int64_t)(c * 3 + k) * gc.n + cb + X] = (T)s;
+      }
     }
   }
 }
 
-// zf[v] (+)= sum over the coarse vertices of v's cell of trilinear weights * ec
-template <typename T, typename C>
+// Trilinear prolongation P: zf (+)= P ec.  A fine vertex takes the mean of the
+// coarse vertices of its coarse cell that it lies between: 1, 2, 4 or 8 of
+// them by the parities of its coordinates.  One block per fine row (y, z); a
+// thread per coarse X writes the fine pair (2X, 2X+1).  The four coarse rows
+// (Y0|Y1) x (Z0|Z1) are always summed, with Y1 = Y0 (Z1 = Z0) for an even y
+// (z): the duplicated terms double exactly, so the quarter of the sum is the
+// mean without any branch.
+template <typename T, typename C, bool OVERWRITE>
 __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __restrict__ ec,
-                               const double* scal, int overwrite) {
+                               const double* scal) {
+  using A = typename Acc<T>::type;
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < gf.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int gx = (int)(i % gf.nx);
-    const int gy = (int)((i / gf.nx) % gf.ny);
-    const int gz = (int)(i / ((int64_t)gf.nx * gf.ny));
-    const int X0 = gx >> 1, Y0 = gy >> 1, Z0 = gz >> 1;
-    const int X1 = (gx & 1) ? (X0 + 1 == gc.nx ? 0 : X0 + 1) : X0;
-    const int Y1 = (gy & 1) ? (Y0 + 1 == gc.ny ? 0 : Y0 + 1) : Y0;
-    const int Z1 = (gz & 1) ? (Z0 + 1 == gc.nz ? 0 : Z0 + 1) : Z0;
-    using A = typename Acc<T>::type;
-    const int nt = 1 << ((gx & 1) + (gy & 1) + (gz & 1));
-    const A w = A(1.0) / A(nt);
-    int64_t idx[8];
-    int m = 0;
-    for (int cz = 0; cz < ((gz & 1) ? 2 : 1); ++cz)
-      for (int cy = 0; cy < ((gy & 1) ? 2 : 1); ++cy)
-        for (int cx = 0; cx < ((gx & 1) ? 2 : 1); ++cx)
-          idx[m++] = (cx ? X1 : X0) + (int64_t)gc.nx * ((cy ? Y1 : Y0) + (int64_t)gc.ny * (cz ? Z1 : Z0));
+  const int row = xcd_row(gf.ny * gf.nz);
+  const int y = row % gf.ny, z = row / gf.ny;
+  const int Y0 = y >> 1, Z0 = z >> 1;
+  const int Y1 = (y & 1) ? (Y0 + 1 == gc.ny ? 0 : Y0 + 1) : Y0;
+  const int Z1 = (z & 1) ? (Z0 + 1 == gc.nz ? 0 : Z0 + 1) : Z0;
+  const int64_t cr[4] = {(int64_t)gc.nx * (Y0 + (int64_t)gc.ny * Z0),
+                         (int64_t)gc.nx * (Y1 + (int64_t)gc.ny * Z0),
+                         (int64_t)gc.nx * (Y0 + (int64_t)gc.ny * Z1),
+                         (int64_t)gc.nx * (Y1 + (int64_t)gc.ny * Z1)};
+  const int64_t fbase = (int64_t)row * gf.nx;
+  for (int X = threadIdx.x; X < gc.nx; X += blockDim.x) {
+    const int X1 = X + 1 == gc.nx ? 0 : X + 1;
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) {
       if (!on[c]) continue;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const C* e = ec + (int64_t)(c * 3 + k) * gc.n;
-        A v = A(0);
-        for (int t = 0; t < m; ++t) v += (A)e[idx[t]];
-        T* o = zf + (int64_t)(c * 3 + k) * gf.n + i;
-        *o = (T)(overwrite ? w * v : (A)*o + w * v);
+        const A s0 = ((A)e[cr[0] + X] + (A)e[cr[1] + X]) + ((A)e[cr[2] + X] + (A)e[cr[3] + X]);
+        const A s1 = ((A)e[cr[0] + X1] + (A)e[cr[1] + X1]) + ((A)e[cr[2] + X1] + (A)e[cr[3] + X1]);
+        const A v0 = A(0.25) * s0, v1 = A(0.125) * (s0 + s1);
+        Pair<T>* o = reinterpret_cast<Pair<T>*>(zf + (int64_t)(c * 3 + k) * gf.n + fbase + 2 * X);
+        Pair<T> p;
+        if (OVERWRITE) {
+          p.v[0] = (T)v0;
+          p.v[1] = (T)v1;
+        } else {
+          p = *o;
+          p.v[0] = (T)((A)p.v[0] + v0);
+          p.v[1] = (T)((A)p.v[1] + v1);
+        }
+        *o = p;
       }
     }
   }
@@ -402,33 +452,37 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
 
 template <typename T, typename W>
 void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 0>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+  hipLaunchKernelGGL((stencil_kernel<T, W, 0>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
                      g, st, u, (const T*)nullptr, (const W*)nullptr, y, (const double*)nullptr,
                      (const double*)nullptr);
 }
 template <typename T, typename W>
 void kc_residual(const Grid& g, const W* st, const T* z, const T* r, T* t, const double* scal,
                  const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 1>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+  hipLaunchKernelGGL((stencil_kernel<T, W, 1>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
                      g, st, z, r, (const W*)nullptr, t, scal, mean);
 }
 template <typename T, typename W>
 void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv, T* zout,
                const double* scal, const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 2>), dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, s,
+  hipLaunchKernelGGL((stencil_kernel<T, W, 2>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
                      g, st, z, r, dinv, zout, scal, mean);
 }
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s) {
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(pw_blocks(gc.n, 256, 8192)), dim3(256), 0, s, gf, gc,
-                     tf, rc, scal);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(gc.ny * gc.nz), dim3(row_threads(gc.nx)), 0, s, gf,
+                     gc, tf, rc, scal);
 }
 template <typename T, typename C>
 void prolong_add(const Grid& gf, const Grid& gc, T* zf, const C* ec, const double* scal,
                  bool overwrite, hipStream_t s) {
-  hipLaunchKernelGGL((prolong_kernel<T, C>), dim3(pw_blocks(gf.n, 256, 8192)), dim3(256), 0, s, gf, gc,
-                     zf, ec, scal, overwrite ? 1 : 0);
+  if (overwrite)
+    hipLaunchKernelGGL((prolong_kernel<T, C, true>), dim3(gf.ny * gf.nz), dim3(row_threads(gc.nx)),
+                       0, s, gf, gc, zf, ec, scal);
+  else
+    hipLaunchKernelGGL((prolong_kernel<T, C, false>), dim3(gf.ny * gf.nz), dim3(row_threads(gc.nx)),
+                       0, s, gf, gc, zf, ec, scal);
 }
 template <typename S, typename T>
 void galerkin_first(const Grid& gf, const Grid& gc, const S* s, const double* msig_dev, T* st,
