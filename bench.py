@@ -217,7 +217,9 @@ def bench_batch(args):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         dofit += float(sum(r.iters[c].sum() * 3 * np.prod(shapes[c]) for c in range(len(shapes))))
-        log(f"step {k}: {times[-1]:.3f} s, max iters {r.iters.max()}, max relres {r.relres.max():.2e}")
+        conv = int((r.relres.max(axis=1) <= args.tol).sum())
+        log(f"step {k}: {times[-1]:.3f} s, max iters {r.iters.max()}, max relres "
+            f"{r.relres.max():.2e}, {conv}/{len(shapes)} cells converged")
     total = sum(times)
     return {
         "metric": "MG-PCG DOF-iters/s, 48 batched cells (sizes 32-128)",
@@ -226,9 +228,12 @@ def bench_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "48 periodic cells, sizes from {32,48,64,96,128}^3, smoothed noise "
-                               "sigma 3, VF U[0.1,0.5], FP32 MG-PCG to 1e-6, cold start, one "
-                               "persistent launch per level-0 pass, captured graphs",
+                               f"sigma 3, VF U[0.1,0.5], FP32 MG-PCG to {args.tol:g} (at most "
+                               f"{args.max_iter} iterations), cold start, one persistent launch "
+                               "per level-0 pass, captured graphs",
                    "cells": [list(s) for s in shapes], "tuned_grid": grid, "tuned_lz": lz},
+        "cells_converged": conv, "pcg_iters_per_cell": r.iters.max(axis=1).tolist(),
+        "max_relres_per_cell": [float(v) for v in r.relres.max(axis=1)],
     }
 
 

@@ -872,14 +872,18 @@ class BatchSolver {
     return Status{};
   }
 
+  // Plans cover the live cells (those with an unconverged case), largest
+  // first; a solve rebuilds them whenever a cell finishes, so that finished
+  // cells cost no launches or items.
   Status build_plans() {
     free_plans();
-    const int B = (int)cells.size();
+    if (live_.empty()) live_ = order_;
+    const int B = (int)live_.size();
     std::vector<Op0BatchCell> mv[2], rs, ps;
     std::vector<PwBatchCell> up[2], jc;
     nblk_ = 1;
-    for (int c : order_) nblk_ = std::max(nblk_, vec_blocks_for(cells[c]->grids_[0].n));
-    for (int c : order_) {
+    for (int c : live_) nblk_ = std::max(nblk_, vec_blocks_for(cells[c]->grids_[0].n));
+    for (int c : live_) {
       S& X = *cells[c];
       const Grid& g = X.grids_[0];
       if (op0_tiles_per_case(g, lz[c]) > X.stride_)
@@ -933,6 +937,7 @@ class BatchSolver {
       return ms / 5.0;
     };
     for (auto& X : cells) scal_set_all_active(X->scal_, st_);
+    live_ = order_;
     // z-chunk, one size class at a time (the others keep their current value)
     std::vector<int> sizes;
     for (auto& X : cells) sizes.push_back(X->grids_[0].nz);
@@ -981,7 +986,10 @@ class BatchSolver {
     const int B = (int)cells.size();
     for (auto& X : cells)
       if (!X->have_density_) return fail(HMG_E_STATE, "a cell has no density");
-    if (!mvp_[0]) HMG_TRY(build_plans());
+    if (!mvp_[0] || live_.size() != cells.size()) {
+      live_ = order_;
+      HMG_TRY(build_plans());
+    }
     destroy_graphs();
     std::vector<std::array<bool, NCASE>> active(B);
     std::vector<std::array<int, NCASE>> count(B);
@@ -1013,8 +1021,24 @@ class BatchSolver {
         cells[c]->last_true_[k] = std::sqrt(h[S_RR * 8 + k]);
       }
     }
+    auto cell_live = [&](int c) {
+      for (int k = 0; k < NCASE; ++k)
+        if (active[c][k]) return true;
+      return false;
+    };
+    // drops finished cells from the plans (and the captured graphs)
+    auto refresh_live = [&]() -> Status {
+      std::vector<int> nl;
+      for (int c : live_)
+        if (cell_live(c)) nl.push_back(c);
+      if (nl.size() == live_.size() || nl.empty()) return Status{};
+      live_ = nl;
+      HMG_TRY(build_plans());
+      return Status{};
+    };
+    HMG_TRY(refresh_live());
     vcycle();
-    for (int c = 0; c < B; ++c) {
+    for (int c : live_) {
       S& X = *cells[c];
       fin_sum(X.part_, S_RZNEW, X.stride_tiles(lz[c]), X.scal_, false, st_);
       (void)hipMemcpyAsync(X.scal_ + S_RZ * 8, X.scal_ + S_RZNEW * 8, sizeof(double) * 8,
@@ -1034,8 +1058,9 @@ class BatchSolver {
       for (int c = 0; c < B; ++c)
         for (int k = 0; k < NCASE; ++k) count[c][k] += active[c][k] ? 1 : 0;
       const bool replace = cfgs[0].replace_every > 0 && it % cfgs[0].replace_every == 0;
-      for (int c = 0; c < B; ++c) HMG_TRY(check_cell(c, replace, active[c]));
+      for (int c : live_) HMG_TRY(check_cell(c, replace, active[c]));
       if (!any_active()) break;
+      HMG_TRY(refresh_live());
       HMG_TRY(run_graph(g2_, [&] { phase2(); }));
     }
     for (int c = 0; c < B; ++c) {
@@ -1076,31 +1101,32 @@ class BatchSolver {
   // matvec, alpha, update, residual norms and means (per parity of p)
   void phase1(int par) {
     launch_matvec(par);
-    for (size_t c = 0; c < cells.size(); ++c) {
+    for (int c : live_) {
       S& X = *cells[c];
       fin_sum(X.part_, S_PQ, X.stride_tiles(lz[c]), X.scal_, false, st_);
       fin_alpha(X.scal_, st_);
     }
-    update_batched(pw_[par], (int)cells.size(), nblk_, st_);
-    for (auto& X : cells) {
-      fin_sum(X->part_, S_RR, nblk_, X->scal_, false, st_);
-      fin_mean(X->part_, nblk_, X->grids_[0].n, X->scal_, st_);
+    update_batched(pw_[par], (int)live_.size(), nblk_, st_);
+    for (int c : live_) {
+      S& X = *cells[c];
+      fin_sum(X.part_, S_RR, nblk_, X.scal_, false, st_);
+      fin_mean(X.part_, nblk_, X.grids_[0].n, X.scal_, st_);
     }
   }
   // preconditioner and beta
   void phase2() {
     vcycle();
-    for (size_t c = 0; c < cells.size(); ++c) {
+    for (int c : live_) {
       S& X = *cells[c];
       fin_sum(X.part_, S_RZNEW, X.stride_tiles(lz[c]), X.scal_, false, st_);
       fin_beta(X.scal_, false, st_);
     }
   }
   void vcycle() {
-    jacobi0_batched(pw_[2], (int)cells.size(), nblk_, st_);
+    jacobi0_batched(pw_[2], (int)live_.size(), nblk_, st_);
     op0_batch_launch(rsp_, cells[0]->mk_, st_);
-    for (auto& Xp : cells) {
-      S& X = *Xp;
+    for (int c : live_) {
+      S& X = *cells[c];
       const Grid& g0 = X.grids_[0];
       const int L = X.levels();
       if (L == 1) continue;  // one-level cells are not batched (rejected at creation)
@@ -1188,16 +1214,18 @@ class BatchSolver {
     op0_batch_free(psp_);
     rsp_ = psp_ = nullptr;
   }
+  // scalars of the live cells (those of finished cells no longer change)
   Status read_all() {
-    for (size_t c = 0; c < cells.size(); ++c)
-      (void)hipMemcpyAsync(hsc_ + c * S_NSLOT * 8, cells[c]->scal_, sizeof(double) * S_NSLOT * 8,
-                           hipMemcpyDeviceToHost, st_);
+    for (int c : live_)
+      (void)hipMemcpyAsync(hsc_ + (size_t)c * S_NSLOT * 8, cells[c]->scal_,
+                           sizeof(double) * S_NSLOT * 8, hipMemcpyDeviceToHost, st_);
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("batch scalar readback");
     return check_hip("batch scalar readback");
   }
 
   hipStream_t st_;
   std::vector<int> order_;
+  std::vector<int> live_;  // cells in the current plans (largest first)
   Op0BatchPlan* mvp_[2] = {nullptr, nullptr};
   Op0BatchPlan *rsp_ = nullptr, *psp_ = nullptr;
   PwBatchCell* pw_[3] = {nullptr, nullptr, nullptr};  // update (2 parities), Jacobi
