@@ -55,9 +55,12 @@ def source_hash(paths=KERNEL_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current level-0 source; else None."""
+def measured_traffic(kernel: str, alg_bytes_per_launch: float):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE of launches with all six cases active, scaled by a plain copy of
+    known size), if it was taken on the current level-0 source; else None.
+    Launches with fewer active cases move proportionally less, so the figure is
+    scaled by the algorithmic bytes of the timed launches."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -65,7 +68,10 @@ def measured_traffic(kernel: str):
         return None
     if t.get("source_sha256_16") != source_hash():
         return None
-    return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["hbm_bytes_per_launch"] * alg_bytes_per_launch / k["algorithmic_bytes_per_launch"]
 
 
 def copy_bandwidth(nbytes=1 << 31, reps=5):
@@ -287,7 +293,7 @@ def main():
     name, (cnt, ms, by) = max(((k, v) for k, v in prof.items() if v[0] > 0),
                               key=lambda kv: kv[1][1])
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    traffic = measured_traffic(name)
+    traffic = measured_traffic(name, by / cnt) if cnt else None
     kernel_table = {k: {"launches": v[0], "ms": round(v[1], 3),
                         "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                     for k, v in prof.items()}
