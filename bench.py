@@ -15,8 +15,9 @@ Prints one JSON line.  value = MG-PCG DOF-iterations per second over the timed
 solves of the first form (3 n DOFs per case x PCG iterations of each case /
 solve wall time); s_per_opt_iter is reported beside it.  --forms adds the
 other forms of the method on the same cell (each gets its own warm-up and
-steps): mixed_bf16 (bf16 multigrid vectors), learned (network warm start with
-the cold start as fallback), cold (zero start every step).  The roofline object
+steps): mixed_bf16 (bf16 multigrid vectors), mixed_bf16_stencil (also bf16
+coarse stencils), learned (network warm start with the cold start as
+fallback), cold (zero start every step).  The roofline object
 covers the level-0 kernel with the largest share of the timed solve time of the
 first form, timed with HIP events on the context stream; its HBM traffic comes
 from the committed rocprofv3 counter summary when that summary was taken on the
@@ -127,7 +128,7 @@ def run_form(form, x0_host, n, args, W, profile):
     from oracle import hmgref as O
     from paper_2301_08911_amd.hmg import Context
     shape = (n, n, n)
-    prec = "mixed_bf16" if form == "mixed_bf16" else "fp32"
+    prec = form if form.startswith("mixed_bf16") else "fp32"
     x = torch.from_numpy(x0_host.astype(np.float32).ravel()).cuda()
     rho, g, gx = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
     ctx = Context(shape, precision=prec, Emin=1e-9)
@@ -250,7 +251,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
     ap.add_argument("--forms", default="plain",
-                    help="comma list of plain, mixed_bf16, learned, cold (first = headline)")
+                    help="comma list of plain, mixed_bf16, mixed_bf16_stencil, learned, cold "
+                         "(the first is the headline)")
     ap.add_argument("--workload", default="cell", choices=["cell", "batch48"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=3000)

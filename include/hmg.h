@@ -71,10 +71,13 @@ typedef enum {
   HMG_MIXED_FP16 = 3,  /* reserved, not built: fp16 vectors cannot hold the
                           smoother corrections of soft regions (1/Emin scale)  */
   HMG_MIXED_BF16_STENCIL = 4 /* HMG_MIXED_BF16 with the coarse stencils and
-                          block inverses also in bf16.  Rounding the stencils
-                          (2^-8) perturbs the near-null-space of the coarse
-                          operators; on high-contrast cells (Emin = 1e-9 with
-                          void) MG-PCG can then stagnate near 1e-2            */
+                          block inverses also in bf16 (Sec. 5: low-precision
+                          stencils, higher-precision vectors).  The centre
+                          block of a rounded stencil is never read: it is
+                          minus the sum of the 26 stored blocks, applied in
+                          difference form, so translations (of the cell or of
+                          a stiff island in void) stay exactly in the null
+                          space and high-contrast cells converge as in FP32 */
 } hmg_precision;
 
 /* Solver configuration (Sec. 6 defaults: E0 = 1, nu = 0.3, p = 3). */

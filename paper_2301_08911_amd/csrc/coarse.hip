@@ -39,6 +39,34 @@ __device__ __forceinline__ bool case_on(const double* scal, int c) {
   return scal == nullptr || scal[S_ACTIVE * 8 + c] != 0.0;
 }
 
+// Rounded (bf16) stencils: a translation t of the whole grid (or of a stiff
+// island floating in Emin-void) costs no energy, so the 27 blocks of a row sum
+// to zero, and rounding each block on its own breaks that.  The centre block
+// is therefore never taken from storage: it is the negated sum of the 26
+// stored off-centre blocks (in FP64), and the operator is applied in the
+// difference form sum_{d != 0} K_d (u_{v+d} - u_v), which keeps every such
+// translation in the null space exactly.  Stencils of wider types keep their
+// stored centre.
+template <typename W>
+constexpr bool kCentreFromSum = std::is_same<W, bf16>::value;
+
+template <typename W>
+__device__ __forceinline__ void centre_block(const W* __restrict__ st, int64_t n, int64_t v,
+                                             double (&c)[9]) {
+  if (kCentreFromSum<W>) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c[t] = 0.0;
+    for (int d = 0; d < 27; ++d) {
+      if (d == 13) continue;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) c[t] -= to_d(st[(int64_t)(d * 9 + t) * n + v]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) c[t] = to_d(st[(int64_t)(13 * 9 + t) * n + v]);
+  }
+}
+
 // Two consecutive values of a row (the even one first): one aligned load or
 // store of 2 * sizeof(T) bytes.  Rows start at even offsets (every grid that
 // is coarsened has even extents), so 2X is always pair-aligned.
@@ -83,6 +111,12 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
     A acc[NCASE][3];
 #pragma unroll
     for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
+    A uc[NCASE][3];  // u at v, subtracted in the difference form
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        uc[c][k] = kCentreFromSum<W> ? (A)(u + (size_t)(c * 3 + k) * n)[i] : A(0);
     // neighbour rows (dy, dz), then the three x offsets of each row
     for (int a = 0; a < 9; ++a) {
       int y = gy + a % 3 - 1, z = gz + a / 3 - 1;
@@ -91,6 +125,7 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
       const int rb = g.nx * (y + g.ny * z);
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
+        if (kCentreFromSum<W> && a == 4 && dx == 1) continue;
         int x = gx + dx - 1;
         x = x < 0 ? x + g.nx : (x == g.nx ? 0 : x);
         const int w = rb + x;
@@ -100,9 +135,9 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
         for (int t = 0; t < 9; ++t) K[t] = (A)(sd + (size_t)t * n)[i];
 #pragma unroll
         for (int c = 0; c < NCASE; ++c) {
-          const A u0 = (A)(u + (size_t)(c * 3 + 0) * n)[w];
-          const A u1 = (A)(u + (size_t)(c * 3 + 1) * n)[w];
-          const A u2 = (A)(u + (size_t)(c * 3 + 2) * n)[w];
+          const A u0 = (A)(u + (size_t)(c * 3 + 0) * n)[w] - uc[c][0];
+          const A u1 = (A)(u + (size_t)(c * 3 + 1) * n)[w] - uc[c][1];
+          const A u2 = (A)(u + (size_t)(c * 3 + 2) * n)[w] - uc[c][2];
           acc[c][0] += K[0] * u0 + K[1] * u1 + K[2] * u2;
           acc[c][1] += K[3] * u0 + K[4] * u1 + K[5] * u2;
           acc[c][2] += K[6] * u0 + K[7] * u1 + K[8] * u2;
@@ -300,6 +335,13 @@ __global__ void galerkin_next_kernel(Grid gf, Grid gc, const T* __restrict__ stf
         if (px < -1 || px > 1 || py < -1 || py > 1 || pz < -1 || pz > 1) continue;
         const double w = wa * (bx ? 0.5 : 1.0) * (by ? 0.5 : 1.0) * (bz ? 0.5 : 1.0);
         const int dp = (px + 1) + 3 * (py + 1) + 9 * (pz + 1);
+        if (kCentreFromSum<T> && dp == 13) {
+          double cb[9];
+          centre_block(stf, gf.n, i, cb);
+#pragma unroll
+          for (int t = 0; t < 9; ++t) blk[t] += w * cb[t];
+          continue;
+        }
 #pragma unroll
         for (int t = 0; t < 9; ++t) blk[t] += w * to_d(stf[(int64_t)(dp * 9 + t) * gf.n + i]);
       }
@@ -316,8 +358,7 @@ __global__ void dinv_stencil_kernel(Grid g, const T* __restrict__ st, double ome
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n;
        i += (int64_t)gridDim.x * blockDim.x) {
     double a[9];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) a[t] = to_d(st[(int64_t)(13 * 9 + t) * g.n + i]);
+    centre_block(st, g.n, i, a);
     const double a00 = a[0], a11 = a[4], a22 = a[8];
     const double a01 = 0.5 * (a[1] + a[3]), a12 = 0.5 * (a[5] + a[7]), a02 = 0.5 * (a[2] + a[6]);
     const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22;
@@ -348,9 +389,15 @@ __global__ void dense_kernel(Grid g, const T* __restrict__ st, double* __restric
       const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
       const int64_t w = modp(gx + dx, g.nx) +
                         (int64_t)g.nx * (modp(gy + dy, g.ny) + (int64_t)g.ny * modp(gz + dz, g.nz));
+      double b[9];
+      if (d == 13) {
+        centre_block(st, g.n, v, b);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 9; ++t) b[t] = to_d(st[(int64_t)(d * 9 + t) * g.n + v]);
+      }
       for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q)
-          A[(3 * v + p) * N + 3 * w + q] += to_d(st[(int64_t)(d * 9 + p * 3 + q) * g.n + v]);
+        for (int q = 0; q < 3; ++q) A[(3 * v + p) * N + 3 * w + q] += b[p * 3 + q];
     }
   }
 }

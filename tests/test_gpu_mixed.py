@@ -145,19 +145,46 @@ def test_mixed_laminate_closed_form():
     assert rel(ctx.elastic_tensor(), ref) < 1e-4
 
 
-def test_mixed_matches_fp32_on_soft_contrast_cell():
-    """Emin = 1e-9 with a 1e-3 floor: the corrections span ~9 decades; the mixed
-    form must still converge and agree with the FP32 form to 1e-4."""
+@pytest.mark.parametrize("vf", [0.3, 0.15])
+def test_mixed_matches_fp32_on_soft_contrast_cell(vf):
+    """Emin = 1e-9 with a 1e-3 floor: the corrections span ~9 decades; both
+    reduced-precision forms must still converge and agree with the FP32 form to
+    1e-4 (the thinner VF 0.15 structure is the harder, more ill-conditioned one)."""
     shape = (64, 64, 64)
-    rho = f32(I.smoothed_noise_density(shape, 3, 0.3, sigma=2.0))
+    rho = f32(I.smoothed_noise_density(shape, 3, vf, sigma=2.0 if vf > 0.2 else 3.0))
     out = {}
-    for prec in ("fp32", "mixed_bf16"):
+    for prec in ("fp32", "mixed_bf16", "mixed_bf16_stencil"):
         ctx = ctx_for(shape, prec)
         ctx.set_density(dev(rho))
-        res = ctx.solve_cases(1e-6, 600)
-        print(prec, res.iters.tolist(), flush=True)
+        res = ctx.solve_cases(1e-6, 1500)
+        print(prec, vf, res.iters.tolist(), flush=True)
         assert res.converged, (prec, res)
         out[prec] = (ctx.elastic_tensor(), res.iters)
-    assert rel(out["mixed_bf16"][0], out["fp32"][0]) < 1e-4
-    # bf16 preconditioner vectors cost at most a few iterations
-    assert out["mixed_bf16"][1].max() <= 1.2 * out["fp32"][1].max() + 10
+    for prec in ("mixed_bf16", "mixed_bf16_stencil"):
+        assert rel(out[prec][0], out["fp32"][0]) < 1e-4, prec
+        # bf16 storage costs at most a few iterations
+        assert out[prec][1].max() <= 1.2 * out["fp32"][1].max() + 10, prec
+
+
+def test_bf16_stencils_keep_translations_in_the_null_space():
+    """Rounded stencils apply their centre block as minus the sum of the stored
+    off-centre blocks (difference form), so K u = 0 holds exactly for a field
+    that is constant per component, on every coarse level, while the stored
+    centre block alone would leave a residue of about 2^-8 |K|."""
+    shape = (32, 32, 32)
+    rho = f32(I.smoothed_noise_density(shape, 4, 0.2, sigma=3.0))
+    ctx = ctx_for(shape, "mixed_bf16_stencil")
+    ctx.set_density(dev(rho))
+    for level in range(1, ctx.num_levels()):
+        dims = ctx.level_dims(level)
+        n = int(np.prod(dims))
+        u = np.zeros((6, 3, n))
+        for c in range(6):
+            for k in range(3):
+                u[c, k] = float((c + 1) * (k + 2))  # exact in bf16
+        y = ctx.apply_operator(level, dev(u.ravel())).cpu().numpy()
+        assert np.abs(y).max() == 0.0, (level, np.abs(y).max())
+        st = ctx.get_stencil(level).cpu().numpy().astype(np.float64).reshape(27, 9, n)
+        # the stored blocks do not sum to zero by themselves (rounding)
+        resid = np.abs(st.sum(axis=0)).max() / np.abs(st).max()
+        print("level", level, "stored row-sum residue", resid, flush=True)
