@@ -126,6 +126,7 @@ void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* di
 template <typename R>
 void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
                         R* r, const double* scal, Partials part, int* nblk_out);
+// Upper bound of the blocks per case of any level-0 pass (FP32 or FP64 tiles).
 int op0_blocks_per_case(const Grid& g);
 
 // Batched level-0 passes (FP32) over many cells in one persistent launch.
@@ -150,6 +151,7 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
 void op0_batch_launch(const Op0BatchPlan* plan, const ModeK<float>& mk, hipStream_t st);
 void op0_batch_free(Op0BatchPlan* plan);
 int op0_batch_items(const Op0BatchPlan* plan);
+// Tiles per case of an FP32 level-0 pass with z-chunk lz (0 = default).
 int op0_tiles_per_case(const Grid& g, int lz);
 
 // Macro-strain loads evaluated in FP64, stored as R; partial ||f||^2 in S_FF.

@@ -6,8 +6,8 @@
 // here it is evaluated element by element in the Walsh-Hadamard mode basis of
 // the 8 nodal values, where K0 has 45 nonzeros instead of 576:
 //   u_hat = H u_e (separable butterflies), w_hat = s_e Kt u_hat, y_e = H w_hat.
-// A workgroup owns a tile of 63 x 7 vertex columns and marches along z.  The
-// vertex plane (tile plus a one-vertex halo) is staged in LDS; each thread owns
+// A workgroup owns a tile of 63 x 15 (FP64: 63 x 7) vertex columns and marches
+// along z.  The vertex plane (tile plus a one-vertex halo) is staged in LDS; each thread owns
 // one element column, forms the x/y butterflies from LDS and the z butterfly
 // in registers against the previous plane, and keeps the z-half of its output
 // that belongs to the next vertex plane in registers.  Lanes run along x, so
@@ -22,13 +22,21 @@
 namespace hmg {
 namespace {
 
-constexpr int TXE = 64;  // element columns along x per tile (one wavefront)
-constexpr int TYE = 8;   // element rows along y per tile (wavefronts per block)
-constexpr int OX = TXE - 1, OY = TYE - 1;  // owned vertex columns per tile
-constexpr int PX = TXE + 1, PY = TYE + 1;  // staged vertex plane
-constexpr int NTHR = TXE * TYE;
-constexpr int NVTX = PY * PX;                       // vertices of a staged plane
-constexpr int NSLOT = (NVTX + NTHR - 1) / NTHR;     // plane vertices per thread
+// Tile of a level-0 pass: TXE element columns (one wavefront) by TYE element
+// rows (one wavefront each).  Every element of a tile is computed, but only
+// the vertices whose eight elements all lie in it are owned, so taller tiles
+// recompute and re-fetch less of their halo: FP32 passes use 16 rows (1024
+// threads), FP64 passes 8 (their register budget allows no more waves).
+template <typename T>
+struct TileShape {
+  static constexpr int TXE = 64;
+  static constexpr int TYE = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int OX = TXE - 1, OY = TYE - 1;  // owned vertex columns per tile
+  static constexpr int PX = TXE + 1, PY = TYE + 1;  // staged vertex plane
+  static constexpr int NTHR = TXE * TYE;
+  static constexpr int NVTX = PY * PX;                    // vertices of a staged plane
+  static constexpr int NSLOT = (NVTX + NTHR - 1) / NTHR;  // plane vertices per thread
+};
 
 struct TileGeom {
   int ntx, nty, nzc, lz, ntiles;
@@ -39,10 +47,12 @@ __host__ __device__ inline int modp(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+template <typename T>
 TileGeom tile_geom(const Grid& g, int lz_req = 0) {
+  using S = TileShape<T>;
   TileGeom t;
-  t.ntx = (g.nx + OX - 1) / OX;
-  t.nty = (g.ny + OY - 1) / OY;
+  t.ntx = (g.nx + S::OX - 1) / S::OX;
+  t.nty = (g.ny + S::OY - 1) / S::OY;
   const int base = t.ntx * t.nty * NCASE;
   int lz = g.nz;
   if (lz_req > 0)
@@ -201,9 +211,10 @@ struct Op0Waves {
 template <typename T, class Op>
 __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const TileGeom& tg,
                                          const ModeK<T>& mk, const T* __restrict__ s, int j) {
-  __shared__ T plane[2][3][PY][PX];
-  __shared__ T rowc[2][3][TYE][TXE];
-  __shared__ double red[NTHR / 64];
+  using S = TileShape<T>;
+  __shared__ T plane[2][3][S::PY][S::PX];
+  __shared__ T rowc[2][3][S::TYE][S::TXE];
+  __shared__ double red[S::NTHR / 64];
 
   const int c = j % NCASE;
   const int tile = j / NCASE;
@@ -216,29 +227,29 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   const int rem = tile / tg.ntx;
   const int ty = rem % tg.nty;
   const int zc = rem / tg.nty;
-  const int x0 = tx * OX, y0 = ty * OY;
+  const int x0 = tx * S::OX, y0 = ty * S::OY;
   const int z0 = zc * tg.lz;
   const int z1 = min(z0 + tg.lz, g.nz);
-  const int tid = threadIdx.x, lx = tid & (TXE - 1), ly = tid / TXE;
+  const int tid = threadIdx.x, lx = tid & (S::TXE - 1), ly = tid / S::TXE;
   const int64_t nxy = (int64_t)g.nx * g.ny;
 
   // Plane-load slots of this thread (same vertices of every plane); each slot
   // produces the three components of one vertex.
-  uint32_t ld_xy[NSLOT];
-  int ld_pos[NSLOT], ld_gx[NSLOT], ld_gy[NSLOT];
-  bool ld_own[NSLOT], ld_ok[NSLOT];
+  uint32_t ld_xy[S::NSLOT];
+  int ld_pos[S::NSLOT], ld_gx[S::NSLOT], ld_gy[S::NSLOT];
+  bool ld_own[S::NSLOT], ld_ok[S::NSLOT];
 #pragma unroll
-  for (int sl = 0; sl < NSLOT; ++sl) {
-    const int i = tid + sl * NTHR;
-    ld_ok[sl] = i < NVTX;
+  for (int sl = 0; sl < S::NSLOT; ++sl) {
+    const int i = tid + sl * S::NTHR;
+    ld_ok[sl] = i < S::NVTX;
     const int ii = ld_ok[sl] ? i : 0;
-    const int py = ii / PX, px = ii - py * PX;
+    const int py = ii / S::PX, px = ii - py * S::PX;
     const int ux = x0 - 1 + px, uy = y0 - 1 + py;
     ld_gx[sl] = modp(ux, g.nx);
     ld_gy[sl] = modp(uy, g.ny);
     ld_xy[sl] = (uint32_t)ld_gx[sl] + (uint32_t)g.nx * (uint32_t)ld_gy[sl];
     ld_pos[sl] = ii;
-    ld_own[sl] = px >= 1 && px <= OX && py >= 1 && py <= OY && ux < g.nx && uy < g.ny;
+    ld_own[sl] = px >= 1 && px <= S::OX && py >= 1 && py <= S::OY && ux < g.nx && uy < g.ny;
   }
   const int ex = modp(x0 - 1 + lx, g.nx), ey = modp(y0 - 1 + ly, g.ny);
   const uint32_t exy = (uint32_t)ex + (uint32_t)g.nx * (uint32_t)ey;
@@ -248,26 +259,26 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   // register sets (fetch); the op's arithmetic and its owned-vertex side writes
   // run when the plane is staged into LDS (stage), so the loads of two planes
   // are in flight behind the compute of one.
-  typename Op::Raw raw0[NSLOT], raw1[NSLOT];
-  auto fetch_plane = [&](int zu, typename Op::Raw(&raw)[NSLOT]) {
+  typename Op::Raw raw0[S::NSLOT], raw1[S::NSLOT];
+  auto fetch_plane = [&](int zu, typename Op::Raw(&raw)[S::NSLOT]) {
     const int64_t zoff = nxy * modp(zu, g.nz);
     const bool ownz = zu >= z0 && zu < z1;
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl)
+    for (int sl = 0; sl < S::NSLOT; ++sl)
       if (ld_ok[sl]) op.fetch(c, zoff, ld_xy[sl], ld_own[sl] && ownz, raw[sl]);
   };
-  auto stage_plane = [&](int buf, int zu, const typename Op::Raw(&raw)[NSLOT]) {
+  auto stage_plane = [&](int buf, int zu, const typename Op::Raw(&raw)[S::NSLOT]) {
     const int gz = modp(zu, g.nz);
     const bool ownz = zu >= z0 && zu < z1;
     const int64_t zoff = nxy * gz;
     T* base = &plane[buf][0][0][0];
 #pragma unroll
-    for (int sl = 0; sl < NSLOT; ++sl)
+    for (int sl = 0; sl < S::NSLOT; ++sl)
       if (ld_ok[sl]) {
         T v[3];
         op.finish(c, zoff, ld_xy[sl], ld_gx[sl], ld_gy[sl], gz, ld_own[sl] && ownz, raw[sl], v);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) base[k * NVTX + ld_pos[sl]] = v[k];
+        for (int k = 0; k < 3; ++k) base[k * S::NVTX + ld_pos[sl]] = v[k];
       }
   };
   auto plane_modes = [&](int buf, T (&tm)[4][3], T (&own)[3]) {
@@ -323,7 +334,7 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   for (int k = 0; k < 3; ++k) rq[k] = uprev[k] = T(0);
 
   auto step = [&](int ez, auto par, T (&tp)[4][3], T (&tn)[4][3],
-                  typename Op::Raw(&rawn)[NSLOT], typename Op::ERaw& e_new,
+                  typename Op::Raw(&rawn)[S::NSLOT], typename Op::ERaw& e_new,
                   const typename Op::ERaw& e_old, T& s_new, const T& s_old) {
     constexpr int cb = decltype(par)::value;  // row buffer read in this step
     constexpr int pb = 1 - cb;                // plane buffer receiving vertex plane ez + 1
@@ -384,17 +395,17 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
     step(ez + 1, Par<1>{}, tb, ta, raw0, eb, ea, sb, sa);
   }
   if (Op::NACC > 0) {
-    const double t0 = block_sum<NTHR / 64>(acc0, red);
+    const double t0 = block_sum<S::NTHR / 64>(acc0, red);
     if (tid == 0) op.part.buf[(op.slot0 * 8 + c) * op.part.stride + tile] = t0;
   }
   if (Op::NACC > 1) {
-    const double t1 = block_sum<NTHR / 64>(acc1, red);
+    const double t1 = block_sum<S::NTHR / 64>(acc1, red);
     if (tid == 0) op.part.buf[(op.slot1 * 8 + c) * op.part.stride + tile] = t1;
   }
 }
 
 template <typename T, class Op>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
+__global__ void __launch_bounds__(TileShape<T>::NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
 op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) {
   op0_body<T, Op>(op, g, tg, mk, s, logical_block());
 }
@@ -413,7 +424,7 @@ struct Op0Cell {
 };
 
 template <typename T, class Op>
-__global__ void __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
+__global__ void __launch_bounds__(TileShape<T>::NTHR) __attribute__((amdgpu_waves_per_eu(Op0Waves<T>::value)))
 op0_batched_kernel(const Op0Cell<T, Op>* __restrict__ cells, const int2* __restrict__ items,
                    int nitems, ModeK<T> mk) {
   const int G = gridDim.x, b = blockIdx.x;
@@ -693,10 +704,10 @@ struct OpForceResidual {
 
 template <typename T, class Op>
 void launch_op0(const Op0Launch<T>& L, const Op& op) {
-  const TileGeom tg = tile_geom(L.g);
+  const TileGeom tg = tile_geom<T>(L.g);
   const int nblk = tg.ntiles * NCASE;
-  hipLaunchKernelGGL((op0_kernel<T, Op>), dim3(nblk), dim3(NTHR), 0, L.stream, op, L.g, tg, L.mk,
-                     L.s);
+  hipLaunchKernelGGL((op0_kernel<T, Op>), dim3(nblk), dim3(TileShape<T>::NTHR), 0, L.stream, op,
+                     L.g, tg, L.mk, L.s);
 }
 
 // ------------------------------------------------------------------ pointwise kernels
@@ -841,8 +852,10 @@ inline int pw_blocks(int64_t n, int tpb, int cap) {
 
 }  // namespace
 
-int op0_blocks_per_case(const Grid& g) { return tile_geom(g).ntiles; }
-int op0_tiles_per_case(const Grid& g, int lz) { return tile_geom(g, lz).ntiles; }
+int op0_blocks_per_case(const Grid& g) {
+  return std::max(tile_geom<float>(g).ntiles, tile_geom<double>(g).ntiles);
+}
+int op0_tiles_per_case(const Grid& g, int lz) { return tile_geom<float>(g, lz).ntiles; }
 
 struct Op0BatchPlan {
   int kind = 0;
@@ -885,7 +898,7 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
       const Op0BatchCell& a = cells[c];
       OpMatvecP<float, float> op{a.in0, a.in1, a.out0, a.out1, a.g.n, a.scal, a.part, S_PQ, 0,
                                  0.f};
-      hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+      hc.push_back({op, a.g, tile_geom<float>(a.g, a.lz), a.s});
     }
     return build_plan(kind, hc, grid, st);
   }
@@ -894,7 +907,7 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
     for (int c = 0; c < ncells; ++c) {
       const Op0BatchCell& a = cells[c];
       OpResidual<float, float> op{a.in0, a.in1, a.out0, a.g.n, a.scal, Partials{}, 0, 0, {}};
-      hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+      hc.push_back({op, a.g, tile_geom<float>(a.g, a.lz), a.s});
     }
     return build_plan(kind, hc, grid, st);
   }
@@ -903,7 +916,7 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
     const Op0BatchCell& a = cells[c];
     OpPostSmooth<float, float> op{a.in0, a.in1, a.in2, a.out0, a.in3, a.g.n, a.scal, a.part,
                                   S_RZNEW, S_QZ, {}};
-    hc.push_back({op, a.g, tile_geom(a.g, a.lz), a.s});
+    hc.push_back({op, a.g, tile_geom<float>(a.g, a.lz), a.s});
   }
   return build_plan(kind, hc, grid, st);
 }
@@ -911,16 +924,16 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
 void op0_batch_launch(const Op0BatchPlan* p, const ModeK<float>& mk, hipStream_t st) {
   if (p->kind == OP0B_MATVEC)
     hipLaunchKernelGGL((op0_batched_kernel<float, OpMatvecP<float, float>>), dim3(p->grid),
-                       dim3(NTHR), 0, st, (const Op0Cell<float, OpMatvecP<float, float>>*)p->cells,
+                       dim3(TileShape<float>::NTHR), 0, st, (const Op0Cell<float, OpMatvecP<float, float>>*)p->cells,
                        p->items, p->nitems, mk);
   else if (p->kind == OP0B_RESIDUAL)
     hipLaunchKernelGGL((op0_batched_kernel<float, OpResidual<float, float>>), dim3(p->grid),
-                       dim3(NTHR), 0, st,
+                       dim3(TileShape<float>::NTHR), 0, st,
                        (const Op0Cell<float, OpResidual<float, float>>*)p->cells, p->items,
                        p->nitems, mk);
   else
     hipLaunchKernelGGL((op0_batched_kernel<float, OpPostSmooth<float, float>>), dim3(p->grid),
-                       dim3(NTHR), 0, st,
+                       dim3(TileShape<float>::NTHR), 0, st,
                        (const Op0Cell<float, OpPostSmooth<float, float>>*)p->cells, p->items,
                        p->nitems, mk);
 }
@@ -947,7 +960,7 @@ void op0_matvec_p(const Op0Launch<T>& L, const V* z, const V* pold, V* pnew, T* 
   // pold that neighbouring blocks must not have overwritten yet.
   OpMatvecP<T, V> op{z, pold, pnew, q, L.g.n, scal, part, S_PQ, 0, T(0)};
   launch_op0(L, op);
-  *nblk_out = tile_geom(L.g).ntiles;
+  *nblk_out = tile_geom<T>(L.g).ntiles;
 }
 
 template <typename T, typename V>
@@ -961,7 +974,7 @@ void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* di
                      const T* q, const double* scal, Partials part, int* nblk_out) {
   OpPostSmooth<T, V> op{z1, r, dinv, zout, q, L.g.n, scal, part, S_RZNEW, S_QZ, {}};
   launch_op0(L, op);
-  *nblk_out = tile_geom(L.g).ntiles;
+  *nblk_out = tile_geom<T>(L.g).ntiles;
 }
 
 template <typename R>
@@ -969,7 +982,7 @@ void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, 
                         R* r, const double* scal, Partials part, int* nblk_out) {
   OpForceResidual<double, R> op{x, r, L.s, tpl, L.g, L.g.n, scal, part, S_FF, S_TRUE};
   launch_op0(L, op);
-  *nblk_out = tile_geom(L.g).ntiles;
+  *nblk_out = tile_geom<double>(L.g).ntiles;
 }
 
 template <typename R>
