@@ -187,6 +187,42 @@ def apply_elementwise(s, shape, K0, u) -> np.ndarray:
     return out[0] if squeeze else out
 
 
+def vertex_neighbourhood(shape, verts):
+    """Index data of [K u]_v at the given vertices (Sec. 4.2, Eq. st-assemb).
+
+    Vertex v is local node a of the element whose origin is v - bits(a), for
+    a = 0..7.  Returns ``elems`` (m, 8): that element for each a, and ``nodes``
+    (m, 8, 8): global vertex of local node b of element ``elems[:, a]``."""
+    nx, ny, nz = shape
+    verts = np.asarray(verts, dtype=np.int64)
+    vx, vy, vz = verts % nx, (verts // nx) % ny, verts // (nx * ny)
+    elems = np.empty((verts.size, 8), dtype=np.int64)
+    nodes = np.empty((verts.size, 8, 8), dtype=np.int64)
+    for a in range(8):
+        a0, a1, a2 = _node_bits(a)
+        ox, oy, oz = (vx - a0) % nx, (vy - a1) % ny, (vz - a2) % nz
+        elems[:, a] = ox + nx * (oy + ny * oz)
+        for b in range(8):
+            b0, b1, b2 = _node_bits(b)
+            nodes[:, a, b] = ((ox + b0) % nx) + nx * (((oy + b1) % ny) + ny * ((oz + b2) % nz))
+    return elems, nodes
+
+
+def apply_at_vertices(K0, s_elems, u_nodes) -> np.ndarray:
+    """[K u]_v = sum_a s_{e_a} sum_b K0[3a:3a+3, 3b:3b+3] u[node_b(e_a)] at m vertices.
+
+    s_elems (m, 8) are the scales of the incident elements of
+    ``vertex_neighbourhood``; u_nodes (c, m, 8, 8, 3) the displacements at their
+    nodes.  Returns (c, m, 3)."""
+    s_elems = np.asarray(s_elems, dtype=np.float64)
+    u_nodes = np.asarray(u_nodes, dtype=np.float64)
+    out = np.zeros(u_nodes.shape[:2] + (3,))
+    for a in range(8):
+        ue = u_nodes[:, :, a].reshape(u_nodes.shape[0], -1, 24)          # (c, m, 24)
+        out += s_elems[None, :, a, None] * (ue @ K0[3 * a:3 * a + 3, :].T)
+    return out
+
+
 def load_vectors(s, shape, K0, chi) -> np.ndarray:
     """f^i = sum_e s_e Q_e^T K0 chi^i for the six cases, shape (6, n, 3)."""
     s = np.asarray(s, dtype=np.float64).ravel()

@@ -1,0 +1,136 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations the
+benchmark times.
+
+* 512^3 FP32 level-0 operator (16-row tiles, 128-plane z-chunks) on the
+  benchmark's density: sampled vertices against the oracle's per-vertex
+  operator, tile, chunk and periodic-seam vertices included.
+* 512^3 FP32 solve of a z-laminate: C^H against the closed form, which holds at
+  any resolution.
+* The 48-cell batch (sizes from {32,48,64,96,128}^3, VF U[0.1,0.5]) with the
+  tuned launch: sampled cells against single-cell solves of the same cells.
+
+The operand of the sampled operator check is a seeded 37^3 random tile
+repeated over the grid (index arithmetic only on both sides), so that the
+oracle needs nothing but the tile and the sampled indices.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hmgref as O
+from paper_2301_08911_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+TILE = 37
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def tile_index(verts, shape):
+    nx, ny, _ = shape
+    x, y, z = verts % nx, (verts // nx) % ny, verts // (nx * ny)
+    return (x % TILE) + TILE * ((y % TILE) + TILE * (z % TILE))
+
+
+def test_operator_512_sampled_vertices():
+    from paper_2301_08911_amd.hmg import Context
+    shape = (N, N, N)
+    n = N ** 3
+    print("operator 512^3 fp32 sampled", flush=True)
+    rho = I.smoothed_noise_density(shape, 0, 0.3, sigma=3.0 * N / 64).astype(np.float32).ravel()
+    tile = I.random_signed_field((TILE, TILE, TILE), 21).astype(np.float32)  # (6, 3, T^3)
+    ctx = Context(shape, precision="fp32")
+    ctx.set_density(torch.from_numpy(rho).cuda())
+    # full operand: u[c, k, v] = tile[c, k, t(v)]
+    v = torch.arange(n, device="cuda", dtype=torch.int64)
+    t = (v % N % TILE) + TILE * ((v // N % N % TILE) + TILE * (v // (N * N) % TILE))
+    del v
+    tile_d = torch.from_numpy(tile.reshape(18, -1)).cuda()
+    u = tile_d[:, t].contiguous()
+    del t
+    y = ctx.apply_operator(0, u.view(-1)).view(18, n)
+    # sampled vertices: tile columns (63), tile rows (15), z-chunks (128), seams
+    r = np.random.default_rng(5)
+    xs = np.array([0, 1, 62, 63, 64, 125, 126, 127, 503, 504, 510, 511])
+    ys = np.array([0, 14, 15, 16, 29, 30, 31, 509, 510, 511])
+    zs = np.array([0, 1, 127, 128, 255, 256, 383, 384, 511])
+    grid_pts = np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
+    pick = grid_pts[r.choice(len(grid_pts), 160, replace=False)]
+    rand = r.integers(0, N, size=(96, 3))
+    pts = np.concatenate([pick, rand])
+    verts = pts[:, 0] + N * (pts[:, 1] + N * pts[:, 2])
+    yg = y[:, torch.from_numpy(verts).cuda()].cpu().numpy().astype(np.float64)  # (18, m)
+    el, nd = O.vertex_neighbourhood(shape, verts)
+    s_el = O.simp_scale(rho.astype(np.float64)[el]).reshape(el.shape)
+    u_nd = tile.reshape(6, 3, -1)[:, :, tile_index(nd, shape)].astype(np.float64)  # (6,3,m,8,8)
+    u_nd = np.moveaxis(u_nd, 1, -1)                                                 # (6,m,8,8,3)
+    ref = O.apply_at_vertices(O.element_stiffness(), s_el, u_nd)                   # (6, m, 3)
+    scale = O.apply_at_vertices(np.abs(O.element_stiffness()), s_el, np.abs(u_nd))
+    got = np.moveaxis(yg.reshape(6, 3, -1), 1, -1)
+    err = np.abs(got - ref)
+    print("max err / scale", (err / scale).max(), flush=True)
+    assert (err <= 2e-6 * scale + 1e-30).all(), (err / scale).max()
+
+
+def test_laminate_512_fp32_closed_form():
+    from paper_2301_08911_amd.hmg import Context
+    from test_gpu_parity import laminate_reference
+    shape = (N, N, N)
+    print("laminate 512^3 fp32", flush=True)
+    prof = np.where((np.arange(N) // 24) % 2 == 0, 1.0, 0.3).astype(np.float32)
+    rho = I.z_laminate(shape, prof).astype(np.float32).ravel()
+    ctx = Context(shape, precision="fp32")
+    ctx.set_density(torch.from_numpy(rho).cuda())
+    res = ctx.solve_cases(1e-6, 400)
+    print("iters", res.iters.tolist(), flush=True)
+    assert res.converged, res
+    C = ctx.elastic_tensor()
+    ref = laminate_reference(O.simp_scale(prof.astype(np.float64)))
+    err = np.linalg.norm(C - ref) / np.linalg.norm(ref)
+    print("relative C^H error", err, flush=True)
+    assert err < 1e-5, err
+
+
+def test_batch48_sampled_cells_match_single_solves():
+    from paper_2301_08911_amd.hmg import Batch, Context
+    sizes = (32, 48, 64, 96, 128)
+    pick = I.uniform01(0, 11, 48)
+    shapes = [(sizes[int(u * 5)],) * 3 for u in pick]
+    vfs = 0.1 + 0.4 * I.uniform01(0, 12, 48)
+    rhos = [torch.from_numpy(I.smoothed_noise_density(s, k, float(vf), sigma=3.0)
+                             .astype(np.float32).ravel()).cuda()
+            for k, (s, vf) in enumerate(zip(shapes, vfs))]
+    print("batch48", flush=True)
+    b = Batch(shapes)
+    for k in range(48):
+        b.set_density(k, rhos[k])
+    b.tune()
+    r = b.solve(1e-6, 3000)
+    Cb = b.elastic_tensors()
+    conv = r.relres.max(axis=1) <= 1e-6
+    print("converged cells", int(conv.sum()), flush=True)
+    # sampled converged cells of every size present
+    chosen = []
+    for sz in sizes:
+        ks = [k for k in range(48) if shapes[k][0] == sz and conv[k]]
+        if ks:
+            chosen.append(ks[0])
+    assert len(chosen) >= 4
+    for k in chosen:
+        ctx = Context(shapes[k], precision="fp32")
+        ctx.set_density(rhos[k])
+        rs = ctx.solve_cases(1e-6, 3000)
+        assert rs.converged
+        C = ctx.elastic_tensor()
+        d = np.linalg.norm(Cb[k] - C) / np.linalg.norm(C)
+        print("cell", k, shapes[k][0], r.iters[k].tolist(), rs.iters.tolist(), d, flush=True)
+        assert d < 1e-5, (k, d)
+        assert (np.abs(r.iters[k] - rs.iters) <= 0.05 * rs.iters + 3).all(), (k, r.iters[k], rs.iters)
+        del ctx

@@ -118,6 +118,25 @@ def test_csr_equals_elementwise_and_kills_translations(K0):
     assert abs(K - K.T).max() < 1e-15
 
 
+def test_operator_at_sampled_vertices_equals_csr(K0):
+    """The per-vertex operator (used for sampled checks of full-size grids)
+    agrees with the assembled periodic CSR matrix, seam vertices included."""
+    shape = (6, 10, 4)
+    rho = I.smoothed_noise_density(shape, 5, 0.3, sigma=1.5)
+    s = O.simp_scale(rho)
+    K = O.assemble_stiffness(s, shape, K0)
+    n = s.size
+    u = I.random_signed_field(shape, 6, ncases=3).transpose(0, 2, 1)     # (3, n, 3)
+    Ku = (K @ u.reshape(3, 3 * n).T).T.reshape(3, n, 3)
+    verts = np.array([0, 5, 6, 59, 60, n - 1, 123, 200, 239])
+    el, nd = O.vertex_neighbourhood(shape, verts)
+    # incident elements are distinct and each contains the vertex as its node a
+    assert all(len(set(row)) == 8 for row in el)
+    assert (nd[:, np.arange(8), np.arange(8)] == verts[:, None]).all()
+    y = O.apply_at_vertices(K0, s[el], u[:, nd])
+    assert np.abs(y - Ku[:, verts]).max() < 1e-13 * np.abs(Ku).max()
+
+
 def test_loads_sum_to_zero_and_vanish_on_uniform_cell(K0, chi):
     shape = (4, 4, 6)
     s = O.simp_scale(I.uniform_density(shape, 1))
