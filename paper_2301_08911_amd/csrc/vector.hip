@@ -56,67 +56,87 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
     }
 }
 
-// r -= alpha q; partials of ||r||^2 and of sum(r) per case and component (the
-// translation component is removed before smoothing).
-template <typename T, typename V>
-__device__ __forceinline__ void update_body(const Grid& g, double* __restrict__ x,
-                                            const V* __restrict__ p, T* __restrict__ r,
-                                            const T* __restrict__ q, const double* scal,
-                                            const Partials& part) {
-  __shared__ double red[(VB / 64) * NCASE * 4];
-  bool on[NCASE];
-  T al[NCASE];
-  double al64[NCASE];
+// r -= alpha q with the iterate advanced every other iteration: the two
+// direction buffers of the matvec still hold p_{k-1} and p_k, so XMODE 1 adds
+// alpha_{k-1} p_{k-1} + alpha_k p_k and XMODE 0 leaves x alone (12 and 36
+// bytes per DOF instead of 32 and 32).  One load case per blockIdx.y: a
+// thread streams the three components of one case, which keeps its registers
+// (and the number of concurrent streams per wave) small.
+template <typename T, int XMODE>
+__device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ x,
+                                            const T* __restrict__ pprev, const T* __restrict__ p,
+                                            T* __restrict__ r, const T* __restrict__ q,
+                                            const double* scal, const Partials& part, int c) {
+  __shared__ double red[(VB / 64) * 4];
+  if (!case_on(scal, c)) {
+    if (threadIdx.x == 0) {
+      part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = 0.0;
 #pragma unroll
-  for (int c = 0; c < NCASE; ++c) {
-    on[c] = case_on(scal, c);
-    al64[c] = scal[S_ALPHA * 8 + c];
-    al[c] = (T)al64[c];
+      for (int k = 0; k < 3; ++k)
+        part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = 0.0;
+    }
+    return;
   }
-  double acc[NCASE * 4];  // [c]: ||r||^2, [6 + 3c + k]: sum r
-#pragma unroll
-  for (int j = 0; j < NCASE * 4; ++j) acc[j] = 0.0;
+  const double al64 = scal[S_ALPHA * 8 + c];
+  const double xa64 = XMODE == 1 ? scal[S_XALPHA * 8 + c] : 0.0;
+  const T al = (T)al64;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // ||r||^2, sum r per component
   const int64_t n = g.n;
+  const int64_t base = (int64_t)c * 3 * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int c = 0; c < NCASE; ++c) {
-      if (!on[c]) continue;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const int64_t o = (int64_t)(c * 3 + k) * n + i;
-        x[o] += al64[c] * to_d(p[o]);
-        const T rv = r[o] - al[c] * q[o];
-        r[o] = rv;
-        acc[c] += (double)rv * (double)rv;
-        acc[NCASE + 3 * c + k] += (double)rv;
-      }
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = base + (int64_t)k * n + i;
+      if (XMODE == 1) x[o] += xa64 * (double)pprev[o] + al64 * (double)p[o];
+      if (XMODE == 2) x[o] += al64 * (double)p[o];
+      const T rv = r[o] - al * q[o];
+      r[o] = rv;
+      acc[0] += (double)rv * (double)rv;
+      acc[1 + k] += (double)rv;
     }
   }
-  block_sum_multi<NCASE * 4>(acc, red);
-  if (threadIdx.x == 0)
+  block_sum_multi<4>(acc, red);
+  if (threadIdx.x == 0) {
+    part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = acc[0];
 #pragma unroll
-    for (int c = 0; c < NCASE; ++c) {
-      part.buf[(S_RR * 8 + c) * part.stride + blockIdx.x] = acc[c];
+    for (int k = 0; k < 3; ++k)
+      part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = acc[1 + k];
+  }
+}
+
+template <typename T, int XMODE>
+__global__ void __launch_bounds__(VB) update2_kernel(Grid g, double* __restrict__ x,
+                                                     const T* __restrict__ pprev,
+                                                     const T* __restrict__ p, T* __restrict__ r,
+                                                     const T* __restrict__ q, const double* scal,
+                                                     Partials part) {
+  update_case<T, XMODE>(g, x, pprev, p, r, q, scal, part, blockIdx.y);
+}
+
+// x += S_XALPHA p for the active cases (one case per blockIdx.y).
+template <typename T>
+__global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict__ x,
+                                                     const T* __restrict__ p, const double* scal) {
+  const int c = blockIdx.y;
+  if (!case_on(scal, c)) return;
+  const double xa = scal[S_XALPHA * 8 + c];
+  const int64_t n = g.n;
+  const int64_t base = (int64_t)c * 3 * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        part.buf[((S_MEAN0 + k) * 8 + c) * part.stride + blockIdx.x] = acc[NCASE + 3 * c + k];
+    for (int k = 0; k < 3; ++k) {
+      const int64_t o = base + (int64_t)k * n + i;
+      x[o] += xa * (double)p[o];
     }
 }
 
-template <typename T, typename V>
-__global__ void __launch_bounds__(VB) update_kernel(Grid g, double* __restrict__ x,
-                                                    const V* __restrict__ p, T* __restrict__ r,
-                                                    const T* __restrict__ q, const double* scal,
-                                                    Partials part) {
-  update_body<T, V>(g, x, p, r, q, scal, part);
-}
-
-// Batched forms: blockIdx.y selects the cell (its own grid-stride loop over
-// blockIdx.x), so one launch covers every cell of a batch.
 __global__ void __launch_bounds__(VB) update_batched_kernel(const PwBatchCell* __restrict__ cells) {
-  const PwBatchCell& ce = cells[blockIdx.y];
-  update_body<float, float>(ce.g, ce.x, ce.p, ce.r, ce.q, ce.scal, ce.part);
+  // blockIdx.y = cell * NCASE + load case; x += alpha p every iteration
+  const PwBatchCell& ce = cells[blockIdx.y / NCASE];
+  update_case<float, 2>(ce.g, ce.x, nullptr, ce.p, ce.r, ce.q, ce.scal, ce.part,
+                        blockIdx.y % NCASE);
 }
 
 // z = Dinv (r - m), m the per-component mean in `mean` (slots S_MEAN*, may be NULL).
@@ -396,7 +416,7 @@ inline int blocks_for(int64_t n) {
 int vec_blocks(const Grid& g) { return blocks_for(g.n); }
 
 void update_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(update_batched_kernel, dim3(nblk, ncells), dim3(VB), 0, st, cells_dev);
+  hipLaunchKernelGGL(update_batched_kernel, dim3(nblk, ncells * NCASE), dim3(VB), 0, st, cells_dev);
 }
 void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(jacobi0_batched_kernel, dim3(nblk, ncells), dim3(VB), 0, st, cells_dev);
@@ -416,20 +436,30 @@ template void vec_convert<float, bf16>(bf16*, const float*, int64_t, hipStream_t
 template void vec_convert<bf16, float>(float*, const bf16*, int64_t, hipStream_t);
 template void vec_convert<bf16, double>(double*, const bf16*, int64_t, hipStream_t);
 
-template <typename T, typename V>
-void vec_update_r(const Grid& g, double* x, const V* p, T* r, const T* q, const double* scal,
-                  Partials part, int* nblk_out, hipStream_t st) {
+template <typename T>
+void vec_update_r2(const Grid& g, double* x, const T* pprev, const T* p, T* r, const T* q,
+                   const double* scal, Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL((update_kernel<T, V>), dim3(nb), dim3(VB), 0, st, g, x, p, r, q, scal, part);
+  if (pprev)
+    hipLaunchKernelGGL((update2_kernel<T, 1>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pprev, p,
+                       r, q, scal, part);
+  else
+    hipLaunchKernelGGL((update2_kernel<T, 0>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pprev, p,
+                       r, q, scal, part);
   *nblk_out = nb;
 }
-template void vec_update_r<float, float>(const Grid&, double*, const float*, float*, const float*,
-                                         const double*, Partials, int*, hipStream_t);
-template void vec_update_r<double, double>(const Grid&, double*, const double*, double*,
-                                           const double*, const double*, Partials, int*,
-                                           hipStream_t);
-template void vec_update_r<float, bf16>(const Grid&, double*, const bf16*, float*, const float*,
-                                        const double*, Partials, int*, hipStream_t);
+template <typename T>
+void vec_flush_x(const Grid& g, double* x, const T* p, const double* scal, hipStream_t st) {
+  hipLaunchKernelGGL((flush_x_kernel<T>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st, g, x, p,
+                     scal);
+}
+template void vec_update_r2<float>(const Grid&, double*, const float*, const float*, float*,
+                                   const float*, const double*, Partials, int*, hipStream_t);
+template void vec_update_r2<double>(const Grid&, double*, const double*, const double*, double*,
+                                    const double*, const double*, Partials, int*, hipStream_t);
+template void vec_flush_x<float>(const Grid&, double*, const float*, const double*, hipStream_t);
+template void vec_flush_x<double>(const Grid&, double*, const double*, const double*,
+                                  hipStream_t);
 
 template <typename R, typename D, typename Z>
 void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,
