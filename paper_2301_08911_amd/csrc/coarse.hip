@@ -179,16 +179,15 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
 
 // Restriction R = P^T (unscaled weights, Sec. 3.3):
 //   rc[V] = sum_{a in {-1,0,1}^3} w(a) tf[2V + a],  w(a) = prod_k (a_k == 0 ? 1 : 1/2).
-// One block per coarse row (Y, Z); a thread per coarse X reads the pair
-// (2X, 2X+1) and the value 2X-1 of each of the 9 fine rows 2Y+{-1,0,1} x
-// 2Z+{-1,0,1}.
+// One block per coarse row (Y, Z) and load case (blockIdx.y); a thread per
+// coarse X reads the pair (2X, 2X+1) and the value 2X-1 of each of the 9 fine
+// rows 2Y+{-1,0,1} x 2Z+{-1,0,1} of the case's three components.
 template <typename T>
 __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* __restrict__ rc,
                                 const double* scal) {
   using A = typename Acc<T>::type;
-  bool on[NCASE];
-#pragma unroll
-  for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  const int c = blockIdx.y;
+  if (!case_on(scal, c)) return;
   const int row = xcd_row(gc.ny * gc.nz);
   const int Y = row % gc.ny, Z = row / gc.ny;
   const int ys[3] = {Y == 0 ? gf.ny - 1 : 2 * Y - 1, 2 * Y, 2 * Y + 1};
@@ -199,9 +198,7 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* _
   const int64_t cb = (int64_t)row * gc.nx;
   for (int X = threadIdx.x; X < gc.nx; X += blockDim.x) {
     const int xm = X == 0 ? gf.nx - 1 : 2 * X - 1;
-#pragma unroll
-    for (int c = 0; c < NCASE; ++c) {
-      if (!on[c]) continue;
+    {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const T* f = tf + (int64_t)(c * 3 + k) * gf.n;
@@ -226,8 +223,9 @@ __global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* _
 
 // Trilinear prolongation P: zf (+)= P ec.  A fine vertex takes the mean of the
 // coarse vertices of its coarse cell that it lies between: 1, 2, 4 or 8 of
-// them by the parities of its coordinates.  One block per fine row (y, z); a
-// thread per coarse X writes the fine pair (2X, 2X+1).  The four coarse rows
+// them by the parities of its coordinates.  One block per fine row (y, z) and
+// load case (blockIdx.y); a thread per coarse X writes the fine pair
+// (2X, 2X+1) of the case's three components.  The four coarse rows
 // (Y0|Y1) x (Z0|Z1) are always summed, with Y1 = Y0 (Z1 = Z0) for an even y
 // (z): the duplicated terms double exactly, so the quarter of the sum is the
 // mean without any branch.
@@ -235,9 +233,8 @@ template <typename T, typename C, bool OVERWRITE>
 __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __restrict__ ec,
                                const double* scal) {
   using A = typename Acc<T>::type;
-  bool on[NCASE];
-#pragma unroll
-  for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  const int c = blockIdx.y;
+  if (!case_on(scal, c)) return;
   const int row = xcd_row(gf.ny * gf.nz);
   const int y = row % gf.ny, z = row / gf.ny;
   const int Y0 = y >> 1, Z0 = z >> 1;
@@ -250,9 +247,7 @@ __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __
   const int64_t fbase = (int64_t)row * gf.nx;
   for (int X = threadIdx.x; X < gc.nx; X += blockDim.x) {
     const int X1 = X + 1 == gc.nx ? 0 : X + 1;
-#pragma unroll
-    for (int c = 0; c < NCASE; ++c) {
-      if (!on[c]) continue;
+    {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const C* e = ec + (int64_t)(c * 3 + k) * gc.n;
@@ -518,18 +513,18 @@ void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s) {
-  hipLaunchKernelGGL(restrict_kernel<T>, dim3(gc.ny * gc.nz), dim3(row_threads(gc.nx)), 0, s, gf,
-                     gc, tf, rc, scal);
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(gc.ny * gc.nz, NCASE), dim3(row_threads(gc.nx)), 0,
+                     s, gf, gc, tf, rc, scal);
 }
 template <typename T, typename C>
 void prolong_add(const Grid& gf, const Grid& gc, T* zf, const C* ec, const double* scal,
                  bool overwrite, hipStream_t s) {
   if (overwrite)
-    hipLaunchKernelGGL((prolong_kernel<T, C, true>), dim3(gf.ny * gf.nz), dim3(row_threads(gc.nx)),
-                       0, s, gf, gc, zf, ec, scal);
+    hipLaunchKernelGGL((prolong_kernel<T, C, true>), dim3(gf.ny * gf.nz, NCASE),
+                       dim3(row_threads(gc.nx)), 0, s, gf, gc, zf, ec, scal);
   else
-    hipLaunchKernelGGL((prolong_kernel<T, C, false>), dim3(gf.ny * gf.nz), dim3(row_threads(gc.nx)),
-                       0, s, gf, gc, zf, ec, scal);
+    hipLaunchKernelGGL((prolong_kernel<T, C, false>), dim3(gf.ny * gf.nz, NCASE),
+                       dim3(row_threads(gc.nx)), 0, s, gf, gc, zf, ec, scal);
 }
 template <typename S, typename T>
 void galerkin_first(const Grid& gf, const Grid& gc, const S* s, const double* msig_dev, T* st,
