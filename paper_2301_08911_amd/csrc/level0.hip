@@ -58,7 +58,9 @@ TileGeom tile_geom(const Grid& g, int lz_req = 0) {
   if (lz_req > 0)
     lz = lz_req < g.nz ? lz_req : g.nz;
   else
-    while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 8192) lz = (lz + 1) / 2;
+    // about 160 blocks per CU: short z-chunks cost halo planes but keep the
+    // blocks of a wave of the grid close together (measured best at 512^3: 16)
+    while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 40960) lz = (lz + 1) / 2;
   t.lz = lz;
   t.nzc = (g.nz + lz - 1) / lz;
   t.ntiles = t.ntx * t.nty * t.nzc;
