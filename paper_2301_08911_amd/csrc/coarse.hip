@@ -177,6 +177,136 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
   }
 }
 
+// The same three modes for a pair of vertices (x0, x0 + 1) per thread, used
+// for FP32 vectors and stencils on rows of even length.  The
+// two vertices share their neighbour columns: per neighbour row and component
+// one paired load (x0, x0 + 1) and two single loads (x0 - 1, x0 + 2) replace
+// six loads, and every stencil coefficient of the pair is one paired load.
+template <typename T, typename W, int MODE>
+__global__ void stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u,
+                                const T* __restrict__ r, const W* __restrict__ dinv,
+                                T* __restrict__ out, const double* scal, const double* mean) {
+  using A = typename Acc<T>::type;
+  bool on[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  const int n = (int)g.n;
+  const int row = xcd_row(g.ny * g.nz);
+  const int gy = row % g.ny, gz = row / g.ny;
+  const int np = g.nx >> 1;
+  for (int px = threadIdx.x; px < np; px += blockDim.x) {
+    const int x0 = 2 * px;
+    const int i = row * g.nx + x0;  // vertex A; vertex B = i + 1
+    A acc[2][NCASE][3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < NCASE; ++c) acc[h][c][0] = acc[h][c][1] = acc[h][c][2] = A(0);
+    const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
+    const int xp = x0 + 2 == g.nx ? 0 : x0 + 2;
+    for (int a = 0; a < 9; ++a) {
+      int y = gy + a % 3 - 1, z = gz + a / 3 - 1;
+      y = y < 0 ? y + g.ny : (y == g.ny ? 0 : y);
+      z = z < 0 ? z + g.nz : (z == g.nz ? 0 : z);
+      const int rb = g.nx * (y + g.ny * z);
+      // coefficients of both vertices for the three x offsets of this row
+      A K[3][2][9];
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const W* sd = st + (size_t)((3 * a + dx) * 9) * n;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const Pair<W> kp = *reinterpret_cast<const Pair<W>*>(sd + (size_t)t * n + i);
+          K[dx][0][t] = (A)kp.v[0];
+          K[dx][1][t] = (A)kp.v[1];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NCASE; ++c) {
+        A uu[4][3];  // columns x0 - 1, x0, x0 + 1, x0 + 2
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T* uk = u + (size_t)(c * 3 + k) * n + rb;
+          const Pair<T> mid = *reinterpret_cast<const Pair<T>*>(uk + x0);
+          uu[0][k] = (A)uk[xm];
+          uu[1][k] = (A)mid.v[0];
+          uu[2][k] = (A)mid.v[1];
+          uu[3][k] = (A)uk[xp];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const A* Kd = K[dx][h];
+            const A* v = uu[h + dx];
+            acc[h][c][0] += Kd[0] * v[0] + Kd[1] * v[1] + Kd[2] * v[2];
+            acc[h][c][1] += Kd[3] * v[0] + Kd[4] * v[1] + Kd[5] * v[2];
+            acc[h][c][2] += Kd[6] * v[0] + Kd[7] * v[1] + Kd[8] * v[2];
+          }
+      }
+    }
+    A D[2][6];
+    if (MODE == 2) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const Pair<W> dp = *reinterpret_cast<const Pair<W>*>(dinv + (size_t)t * n + i);
+        D[0][t] = (A)dp.v[0];
+        D[1][t] = (A)dp.v[1];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      if (!on[c]) continue;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        Pair<T>* o = reinterpret_cast<Pair<T>*>(out + (size_t)(c * 3 + k) * n + i);
+        if (MODE == 0) {
+          Pair<T> w;
+          w.v[0] = (T)acc[0][c][k];
+          w.v[1] = (T)acc[1][c][k];
+          *o = w;
+        }
+      }
+      if (MODE != 0) {
+        A res[2][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const Pair<T> rp = *reinterpret_cast<const Pair<T>*>(r + (size_t)(c * 3 + k) * n + i);
+          const double m = mean[(S_MEAN0 + k) * 8 + c];
+          res[0][k] = (A)(to_d(rp.v[0]) - m) - acc[0][c][k];
+          res[1][k] = (A)(to_d(rp.v[1]) - m) - acc[1][c][k];
+        }
+        if (MODE == 1) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            Pair<T> w;
+            w.v[0] = (T)res[0][k];
+            w.v[1] = (T)res[1][k];
+            *reinterpret_cast<Pair<T>*>(out + (size_t)(c * 3 + k) * n + i) = w;
+          }
+        } else {
+          A zz[2][3];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const A* Dh = D[h];
+            zz[h][0] = Dh[0] * res[h][0] + Dh[3] * res[h][1] + Dh[5] * res[h][2];
+            zz[h][1] = Dh[3] * res[h][0] + Dh[1] * res[h][1] + Dh[4] * res[h][2];
+            zz[h][2] = Dh[5] * res[h][0] + Dh[4] * res[h][1] + Dh[2] * res[h][2];
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const Pair<T> up = *reinterpret_cast<const Pair<T>*>(u + (size_t)(c * 3 + k) * n + i);
+            Pair<T> w;
+            w.v[0] = (T)((A)up.v[0] + zz[0][k]);
+            w.v[1] = (T)((A)up.v[1] + zz[1][k]);
+            *reinterpret_cast<Pair<T>*>(out + (size_t)(c * 3 + k) * n + i) = w;
+          }
+        }
+      }
+    }
+  }
+}
+
 // Restriction R = P^T (unscaled weights, Sec. 3.3):
 //   rc[V] = sum_{a in {-1,0,1}^3} w(a) tf[2V + a],  w(a) = prod_k (a_k == 0 ? 1 : 1/2).
 // One block per coarse row (Y, Z) and load case (blockIdx.y); a thread per
@@ -492,24 +622,44 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
 
 }  // namespace
 
+// Paired-vertex stencil passes: FP32 vectors and stencils (the pair's
+// registers fit without spilling only there) and an even row.
+template <typename T, typename W>
+inline bool use_pairs(const Grid& g) {
+  return std::is_same<T, float>::value && std::is_same<W, float>::value && g.nx % 2 == 0;
+}
 template <typename T, typename W>
 void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 0>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
-                     g, st, u, (const T*)nullptr, (const W*)nullptr, y, (const double*)nullptr,
-                     (const double*)nullptr);
+  if (use_pairs<T, W>(g))
+    hipLaunchKernelGGL((stencil2_kernel<T, W, 0>), dim3(g.ny * g.nz), dim3(row_threads(g.nx / 2)),
+                       0, s, g, st, u, (const T*)nullptr, (const W*)nullptr, y,
+                       (const double*)nullptr, (const double*)nullptr);
+  else
+    hipLaunchKernelGGL((stencil_kernel<T, W, 0>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
+                       g, st, u, (const T*)nullptr, (const W*)nullptr, y, (const double*)nullptr,
+                       (const double*)nullptr);
 }
 template <typename T, typename W>
 void kc_residual(const Grid& g, const W* st, const T* z, const T* r, T* t, const double* scal,
                  const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 1>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
-                     g, st, z, r, (const W*)nullptr, t, scal, mean);
+  if (use_pairs<T, W>(g))
+    hipLaunchKernelGGL((stencil2_kernel<T, W, 1>), dim3(g.ny * g.nz), dim3(row_threads(g.nx / 2)),
+                       0, s, g, st, z, r, (const W*)nullptr, t, scal, mean);
+  else
+    hipLaunchKernelGGL((stencil_kernel<T, W, 1>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
+                       g, st, z, r, (const W*)nullptr, t, scal, mean);
 }
 template <typename T, typename W>
 void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv, T* zout,
                const double* scal, const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL((stencil_kernel<T, W, 2>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
-                     g, st, z, r, dinv, zout, scal, mean);
+  if (use_pairs<T, W>(g))
+    hipLaunchKernelGGL((stencil2_kernel<T, W, 2>), dim3(g.ny * g.nz), dim3(row_threads(g.nx / 2)),
+                       0, s, g, st, z, r, dinv, zout, scal, mean);
+  else
+    hipLaunchKernelGGL((stencil_kernel<T, W, 2>), dim3(g.ny * g.nz), dim3(row_threads(g.nx)), 0, s,
+                       g, st, z, r, dinv, zout, scal, mean);
 }
+
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s) {
