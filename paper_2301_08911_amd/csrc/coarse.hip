@@ -178,14 +178,15 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
 }
 
 // The same three modes for a pair of vertices (x0, x0 + 1) per thread, used
-// for FP32 vectors and stencils on rows of even length.  The
+// for FP32 stencils on rows of even length.  The
 // two vertices share their neighbour columns: per neighbour row and component
 // one paired load (x0, x0 + 1) and two single loads (x0 - 1, x0 + 2) replace
 // six loads, and every stencil coefficient of the pair is one paired load.
 template <typename T, typename W, int MODE>
-__global__ void stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u,
-                                const T* __restrict__ r, const W* __restrict__ dinv,
-                                T* __restrict__ out, const double* scal, const double* mean) {
+__global__ void __launch_bounds__(256)
+stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u, const T* __restrict__ r,
+                const W* __restrict__ dinv, T* __restrict__ out, const double* scal,
+                const double* mean) {
   using A = typename Acc<T>::type;
   bool on[NCASE];
 #pragma unroll
@@ -622,11 +623,12 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
 
 }  // namespace
 
-// Paired-vertex stencil passes: FP32 vectors and stencils (the pair's
-// registers fit without spilling only there) and an even row.
+// Paired-vertex stencil passes: FP32 stencils with FP32 or bf16 vectors, and
+// an even row.
 template <typename T, typename W>
 inline bool use_pairs(const Grid& g) {
-  return std::is_same<T, float>::value && std::is_same<W, float>::value && g.nx % 2 == 0;
+  return (std::is_same<T, float>::value || std::is_same<T, bf16>::value) &&
+         std::is_same<W, float>::value && g.nx % 2 == 0;
 }
 template <typename T, typename W>
 void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s) {
