@@ -31,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -48,11 +49,16 @@ def log(msg: str):
 
 
 def source_hash(paths=KERNEL_SOURCES):
-    """Short digest of the level-0 kernel sources (ties counter data to a build)."""
+    """Short digest of the level-0 kernel sources without their comments and
+    blank lines (ties counter data to the code that was measured)."""
     h = hashlib.sha256()
     for p in paths:
-        with open(p, "rb") as fh:
-            h.update(fh.read())
+        with open(p, encoding="utf-8") as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

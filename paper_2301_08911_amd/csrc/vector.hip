@@ -56,10 +56,12 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
     }
 }
 
-// r -= alpha q with the iterate advanced every other iteration: the two
-// direction buffers of the matvec still hold p_{k-1} and p_k, so XMODE 1 adds
-// alpha_{k-1} p_{k-1} + alpha_k p_k and XMODE 0 leaves x alone (12 and 36
-// bytes per DOF instead of 32 and 32).  One load case per blockIdx.y: a
+// r -= alpha q for load case c, with partials of ||r||^2 and of sum r per
+// component.  The single-cell solver advances the iterate every other
+// iteration: the two direction buffers of the matvec still hold p_{k-1} and
+// p_k, so XMODE 1 adds alpha_{k-1} p_{k-1} + alpha_k p_k and XMODE 0 leaves x
+// alone (36 and 12 bytes per DOF instead of 32 and 32); XMODE 2 is the plain
+// x += alpha_k p_k of the batched solver.  One load case per block row: a
 // thread streams the three components of one case, which keeps its registers
 // (and the number of concurrent streams per wave) small.
 template <typename T, int XMODE>
