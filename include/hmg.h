@@ -260,7 +260,9 @@ hmg_status hmg_vcycle(hmg_ctx ctx, const void* r_dev, void* z_dev);
 
 /* Grid transfer between level l and l+1: direction 0 restricts (R = P^T) a
  * level-l field into a level-(l+1) field; direction 1 prolongates (P) a
- * level-(l+1) field into a level-l field (overwriting it). */
+ * level-(l+1) field into a level-l field (overwriting it).  The output of
+ * direction 1 is written two values at a time: out_dev must be aligned to
+ * twice the field element size (HMG_E_INVALID otherwise). */
 hmg_status hmg_transfer(hmg_ctx ctx, int32_t level, int32_t direction, const void* in_dev,
                         void* out_dev);
 

@@ -666,6 +666,9 @@ class Solver final : public SolverIface {
       restrict_to<V>(gf, gc, t_, lev_[level + 1].r, nullptr, st_);
       vec_convert<V, T>((T*)out, lev_[level + 1].r, Fc, st_);
     } else {
+      if (reinterpret_cast<uintptr_t>(out) % (2 * sizeof(T)) != 0)
+        return fail(HMG_E_INVALID, "transfer output must be aligned to %d bytes",
+                    (int)(2 * sizeof(T)));
       vec_convert<T, V>(lev_[level + 1].z, (const T*)in, Fc, st_);
       prolong_add<T, V>(gf, gc, (T*)out, lev_[level + 1].z, nullptr, true, st_);
     }

@@ -272,6 +272,14 @@ def test_error_paths():
     ctx.set_density(dev(rho))
     res = ctx.solve_cases(1e-6, 2)
     assert not res.converged and (res.iters == 2).all()
+    # a prolongation output that is not aligned to two values is refused
+    nf = 4096
+    e = torch.zeros(18 * nf // 8, device="cuda")
+    buf = torch.zeros(18 * nf + 1, device="cuda")
+    with pytest.raises(HmgError) as err:
+        ctx.transfer(0, 1, e, out=buf[1:])
+    assert err.value.status == E_INVALID
+    ctx.transfer(0, 1, e, out=buf[:-1])
     with pytest.raises(HmgError):
         ctx_for((16, 16, 6), "fp32")       # 6 -> 3 stops coarsening; coarsest too large?
     with pytest.raises(HmgError):
