@@ -1,7 +1,7 @@
 """GPU parity at the benchmark's full sizes, in the launch configurations the
 benchmark times.
 
-* 512^3 FP32 level-0 operator (16-row tiles, 128-plane z-chunks) on the
+* 512^3 FP32 level-0 operator (16-row tiles, 16-plane z-chunks) on the
   benchmark's density: sampled vertices against the oracle's per-vertex
   operator, tile, chunk and periodic-seam vertices included.
 * 512^3 FP32 solve of a z-laminate: C^H against the closed form, which holds at
@@ -56,11 +56,11 @@ def test_operator_512_sampled_vertices():
     u = tile_d[:, t].contiguous()
     del t
     y = ctx.apply_operator(0, u.view(-1)).view(18, n)
-    # sampled vertices: tile columns (63), tile rows (15), z-chunks (128), seams
+    # sampled vertices: tile columns (63), tile rows (15), z-chunk ends (16k), seams
     r = np.random.default_rng(5)
     xs = np.array([0, 1, 62, 63, 64, 125, 126, 127, 503, 504, 510, 511])
     ys = np.array([0, 14, 15, 16, 29, 30, 31, 509, 510, 511])
-    zs = np.array([0, 1, 127, 128, 255, 256, 383, 384, 511])
+    zs = np.array([0, 1, 15, 16, 127, 128, 255, 256, 383, 384, 511])
     grid_pts = np.stack(np.meshgrid(xs, ys, zs, indexing="ij"), -1).reshape(-1, 3)
     pick = grid_pts[r.choice(len(grid_pts), 160, replace=False)]
     rand = r.integers(0, N, size=(96, 3))
