@@ -44,6 +44,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_08911_amd", "csrc", f)
                   for f in ("level0.hip", "vector.hip", "hmg_internal.hpp")]
 
 
+def bulk_weights():
+    """dF/dC^H of F = -bulk modulus = -(1/9) sum_{i,j<3} C_ij (Voigt order 11,22,33,...)."""
+    import numpy as np
+    W = np.zeros((6, 6))
+    W[:3, :3] = -1.0 / 9.0
+    return W
+
+
+def bulk_modulus(C):
+    return float(C[:3, :3].sum()) / 9.0
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -131,7 +143,6 @@ def run_form(form, x0_host, n, args, W, profile):
     """Warm-up and timed optimization steps of one form; returns its record."""
     import numpy as np
     import torch
-    from oracle import hmgref as O
     from paper_2301_08911_amd.hmg import Context
     shape = (n, n, n)
     prec = form if form.startswith("mixed_bf16") else "fp32"
@@ -167,7 +178,7 @@ def run_form(form, x0_host, n, args, W, profile):
 
     for w in range(args.warmup):
         res, ts, C = opt_step(w == 0)
-        log(f"{form} warmup {w}: iters {res.iters.tolist()} solve {ts:.3f} s B {O.bulk_modulus(C):.6f}")
+        log(f"{form} warmup {w}: iters {res.iters.tolist()} solve {ts:.3f} s B {bulk_modulus(C):.6f}")
     torch.cuda.synchronize()
     if profile:
         ctx.profile(True)
@@ -179,7 +190,7 @@ def run_form(form, x0_host, n, args, W, profile):
         solve_s += ts
         iters_all.append(res.iters.tolist())
         relres_max = max(relres_max, float(res.relres.max()))
-        Bs.append(O.bulk_modulus(C))
+        Bs.append(bulk_modulus(C))
         log(f"{form} step {k}: iters {res.iters.tolist()} relres max {res.relres.max():.2e} "
             f"solve {ts:.3f} s B {Bs[-1]:.6f} converged {res.converged}")
     torch.cuda.synchronize()
@@ -275,7 +286,6 @@ def main():
 
     import numpy as np
     import torch
-    from oracle import hmgref as O
     from paper_2301_08911_amd import inputs as I
 
     torch.cuda.set_device(0)
@@ -287,7 +297,7 @@ def main():
     t = time.perf_counter()
     x_host = I.smoothed_noise_density((n, n, n), args.seed, 0.3, sigma=sigma)
     log(f"  done in {time.perf_counter() - t:.1f} s")
-    W = O.bulk_weights()
+    W = bulk_weights()
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     records, prof, levels = {}, None, 0
     for i, form in enumerate(forms):
