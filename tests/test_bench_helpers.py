@@ -41,3 +41,13 @@ def test_committed_traffic_scales_with_the_launch():
     half = bench.measured_traffic("matvec", 0.5 * k["algorithmic_bytes_per_launch"])
     assert abs(half - 0.5 * k["hbm_bytes_per_launch"]) < 1e-6 * k["hbm_bytes_per_launch"]
     assert bench.measured_traffic("no_such_kernel", 1.0) is None
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_use():
+    import subprocess
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300,
+                         env={**os.environ, "HIP_VISIBLE_DEVICES": ""})
+    assert res.returncode == 2
+    assert "one GPU" in res.stdout + res.stderr
+    assert res.stdout.strip() == "" or not res.stdout.lstrip().startswith("{")
