@@ -35,6 +35,9 @@
  *   - Calls enqueue on the context's HIP stream.  Calls with host outputs
  *     (iters_out, relres_out, C_out, lambda_out, status checks of
  *     hmg_set_density) synchronize that stream before returning.
+ *   - The library keeps no mutable process-wide state: separate contexts may
+ *     be created and used from different host threads.  Calls on one context
+ *     must not overlap.
  *   - Errors are reported by status code only; nothing throws across the ABI.
  *     hmg_last_error() gives a per-context message.  Argument errors leave the
  *     context state unchanged.

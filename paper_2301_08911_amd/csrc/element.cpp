@@ -58,7 +58,7 @@ int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen
         }
 
   // ---- mode form Kt = H K0 H / 64
-  static double Kt[24][24];
+  double Kt[24][24];
   auto H = [](int a, int m) { return (__builtin_popcount(a & m) & 1) ? -1.0 : 1.0; };
   for (int m = 0; m < 8; ++m)
     for (int k = 0; k < 3; ++k)
@@ -79,7 +79,7 @@ int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen
   mk.fg = Kt[11][11] - mk.g;
   mk.z = Kt[21][21];
   // Rebuild Kt from the block pattern and require an exact match.
-  static double R[24][24];
+  double R[24][24];
   std::memset(R, 0, sizeof(R));
   auto I = [](int m, int k) { return 3 * m + k; };
   const int normal[3] = {I(1, 0), I(2, 1), I(4, 2)};
