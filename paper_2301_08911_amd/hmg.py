@@ -72,16 +72,16 @@ class Context:
 
     def _field(self, t: torch.Tensor, n: int | None = None, name="field") -> torch.Tensor:
         n = self.n if n is None else n
-        if t.device.type != "cuda" or t.dtype != self.field_dtype or not t.is_contiguous() \
+        if t.device != self.device or t.dtype != self.field_dtype or not t.is_contiguous() \
                 or t.numel() != 18 * n:
-            raise ValueError(f"{name} must be a contiguous {self.field_dtype} CUDA tensor "
-                             f"with 6*3*{n} elements")
+            raise ValueError(f"{name} must be a contiguous {self.field_dtype} tensor on "
+                             f"{self.device} with 6*3*{n} elements")
         return t
 
     def _scalar(self, t: torch.Tensor, name="array") -> torch.Tensor:
-        if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous() \
+        if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous() \
                 or t.numel() != self.n:
-            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor with n elements")
+            raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device} with n elements")
         return t
 
     def new_field(self, level: int = 0) -> torch.Tensor:
@@ -218,6 +218,7 @@ class Batch:
                  stream: torch.cuda.Stream | None = None):
         self.lib = _lib.load()
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.device = torch.device("cuda", torch.cuda.current_device())
         # graphs cannot be captured on the legacy default stream: own a stream
         self.stream = stream if stream is not None else torch.cuda.Stream()
         cfg = _lib.HmgConfig(0, 0, 0, E0, nu, penal, Emin, 0, 0.0, 1, 1, PRECISIONS["fp32"],
@@ -248,8 +249,10 @@ class Batch:
 
     def set_density(self, cell: int, rho: torch.Tensor):
         nx, ny, nz = self.shapes[cell]
-        if rho.dtype != torch.float32 or not rho.is_contiguous() or rho.numel() != nx * ny * nz:
-            raise ValueError("rho must be a contiguous float32 tensor of the cell's size")
+        if rho.device != self.device or rho.dtype != torch.float32 or not rho.is_contiguous() \
+                or rho.numel() != nx * ny * nz:
+            raise ValueError(f"rho must be a contiguous float32 tensor on {self.device} "
+                             "of the cell's size")
         self.stream.wait_stream(torch.cuda.current_stream())
         self._check(self.lib.hmg_batch_set_density(self._h, cell, _ptr(rho)))
 
