@@ -382,6 +382,36 @@ def test_oc_hits_volume_and_respects_limits():
     assert all(a >= b - 1e-15 for a, b in zip(means, means[1:]))
 
 
+def test_oc_closed_form_with_both_move_limits_active():
+    # Three groups at x = 0.3: g = 0 (update 0, held by the lower move limit at
+    # x - m), g = -1e6 (held by the upper move limit at x + m) and a free group
+    # g = -(1 + 0.2 u).  The volume constraint then fixes lambda in closed form:
+    # sqrt(lambda) = sum_free x sqrt(-g) / (N V - sum_lower (x - m) - sum_upper (x + m)).
+    rng = np.random.default_rng(9)
+    N, V, m = 4096, 0.3, 0.05
+    x = np.full(N, 0.3)
+    g = np.empty(N)
+    g[:512] = 0.0
+    g[512:1024] = -1e6
+    u = rng.uniform(-1.0, 1.0, N - 1024)
+    g[1024:] = -(1.0 + 0.2 * u)
+    xn, lam = O.oc_update(x, g, V, move=m, damp=0.5, xmin=1e-3)
+    sq = (x[1024:] * np.sqrt(-g[1024:])).sum() / (N * V - 512 * (0.3 - m) - 512 * (0.3 + m))
+    assert abs(lam / sq ** 2 - 1) < 1e-12
+    free = x[1024:] * np.sqrt(-g[1024:] / sq ** 2)
+    assert (np.abs(free - 0.3) < m - 1e-3).all()          # the free group is really free
+    assert np.abs(xn[:512] - (0.3 - m)).max() < 1e-15
+    assert np.abs(xn[512:1024] - (0.3 + m)).max() < 1e-15
+    assert np.abs(xn[1024:] - free).max() < 1e-12
+    # damping 1 (narrower spread, so that the free group stays free):
+    # lambda = sum_free x (-g) / (N V - sum_lower (x - m) - sum_upper (x + m))
+    g[1024:] = -(1.0 + 0.1 * u)
+    xn1, lam1 = O.oc_update(x, g, V, move=m, damp=1.0, xmin=1e-3)
+    s1 = (x[1024:] * -g[1024:]).sum() / (N * V - 512 * (0.3 - m) - 512 * (0.3 + m))
+    assert abs(lam1 / s1 - 1) < 1e-12
+    assert np.abs(xn1[1024:] - x[1024:] * -g[1024:] / s1).max() < 1e-12
+
+
 # --------------------------------------------------------------------- multigrid reference
 
 def test_prolongation_reproduces_constants_and_galerkin_kills_translations(K0):
