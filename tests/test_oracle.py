@@ -10,6 +10,7 @@ import os
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from oracle import hmgref as O
 from paper_2301_08911_amd import inputs as I
@@ -427,6 +428,33 @@ def test_prolongation_reproduces_constants_and_galerkin_kills_translations(K0):
     st = O.stencil_blocks(Kc, (4, 2, 3))
     # at a coarse dim of 2 the +1 and -1 neighbours alias; only the sum is defined
     assert st.shape == (27, 3, 3, nc)
+
+
+def test_stencil_blocks_recover_a_random_nonsymmetric_operator():
+    # Assemble a random periodic 27-point operator with 3x3 blocks from its
+    # coefficients st[d, i, j, v] (d = (dx+1) + 3 (dy+1) + 9 (dz+1), row 3v+i,
+    # column 3(v+d)+j), then read the coefficients back.  Axes of 3, 4 and 5
+    # keep the 27 neighbours distinct; the operator is not symmetric, so a
+    # transposed block or a swapped axis shows.
+    shape = (3, 4, 5)
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    st = np.random.default_rng(8).standard_normal((27, 3, 3, n))
+    grid = np.arange(n).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)
+                nb = np.roll(grid, shift=(-dz, -dy, -dx), axis=(0, 1, 2)).ravel()
+                for i in range(3):
+                    for j in range(3):
+                        rows.append(3 * np.arange(n) + i)
+                        cols.append(3 * nb + j)
+                        vals.append(st[d, i, j])
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(3 * n, 3 * n))
+    assert np.array_equal(O.stencil_blocks(A, shape), st)
 
 
 def test_prolongation_interpolates_linear_in_interior():
