@@ -337,6 +337,24 @@ def test_sensitivity_euler_identity():
         assert abs((rho * g).sum() - 3.0 * C[i, j]) < 1e-12 * max(1.0, abs(C).max())
 
 
+@pytest.mark.parametrize("E,nu", [(1.0, 0.3), (2.5, 0.2), (1.0, -0.4)])
+def test_objective_weights_give_textbook_moduli(E, nu):
+    # On the isotropic base tensor the bulk objective is minus the bulk modulus
+    # E / (3 (1 - 2 nu)) and the shear objective minus the shear modulus
+    # E / (2 (1 + nu)); bulk_modulus is the same average as the bulk objective.
+    D = O.constitutive_matrix(E, nu)
+    assert abs(-(O.bulk_weights() * D).sum() - E / (3 * (1 - 2 * nu))) < 1e-14 * E
+    assert abs(-(O.shear_weights() * D).sum() - E / (2 * (1 + nu))) < 1e-14 * E
+    assert abs(O.bulk_modulus(D) - E / (3 * (1 - 2 * nu))) < 1e-14 * E
+    # a shear-only tensor has no bulk part and vice versa
+    S = np.zeros((6, 6))
+    S[3, 3] = S[4, 4] = S[5, 5] = 1.0
+    assert (O.bulk_weights() * S).sum() == 0.0
+    B = np.zeros((6, 6))
+    B[:3, :3] = 1.0
+    assert (O.shear_weights() * B).sum() == 0.0
+
+
 def test_sensitivity_sign_for_stiffness_objectives(random_cell):
     shape, rho, s, u, C = random_cell
     K0, chi = O.element_stiffness(), O.unit_strain_displacements()
