@@ -116,3 +116,13 @@ def test_round_bf16_matches_torch_and_bounds():
     assert np.array_equal(N.round_bf16(a), ref)
     f = a.astype(np.float32).astype(np.float64)
     assert np.all(np.abs(N.round_bf16(a) - f) <= 2.0 ** -8 * np.abs(f))
+    # exact ties (low half 0x8000) round to the even bf16, for even and odd upper
+    # halves and both signs; random values almost never hit a tie
+    hi = np.arange(0x3F00, 0x3F40, dtype=np.uint32)
+    ties = ((hi << 16) | 0x8000).view(np.float32)
+    ties = np.concatenate([ties, -ties])
+    ref = torch.from_numpy(ties).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(N.round_bf16(ties.astype(np.float64)), ref)
+    up = ties.view(np.uint32) >> 16
+    assert np.array_equal(ref.astype(np.float32).view(np.uint32) >> 16,
+                          np.where(up & 1, up + 1, up).astype(np.uint32))

@@ -1,0 +1,97 @@
+"""The oracle's pins catch plausible mistakes (CPU only).
+
+Each case plants one mistake in a temporary copy of the oracle: a dropped
+factor, a wrong sign, exponent or index, or swapped axes.  It then runs the
+pins of that oracle module in a fresh process, and at least one pin must fail.
+The repository's own oracle is never modified.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# (oracle module, pin module, original text, planted mistake)
+MUTATIONS = {
+    # solver oracle
+    "node y/z offsets swapped": (
+        "hmgref", "test_oracle",
+        "((Y + a1) % ny) + ny * ((Z + a2) % nz)", "((Y + a2) % ny) + ny * ((Z + a1) % nz)"),
+    "prolongation weights 1/4, 3/4": (
+        "hmgref", "test_oracle",
+        "return [((f - 1) // 2, 0.5), (((f + 1) // 2) % nc, 0.5)]",
+        "return [((f - 1) // 2, 0.25), (((f + 1) // 2) % nc, 0.75)]"),
+    "prolongation neighbour off by one": (
+        "hmgref", "test_oracle", "(((f + 1) // 2) % nc, 0.5)", "(((f + 3) // 2) % nc, 0.5)"),
+    "load sign": (
+        "hmgref", "test_oracle", "fe = np.outer(s, K0 @ chi[i])", "fe = -np.outer(s, K0 @ chi[i])"),
+    "C^H without 1/n": (
+        "hmgref", "test_oracle",
+        'return np.einsum("n,nij->ij", s, Ee) / s.size', 'return np.einsum("n,nij->ij", s, Ee)'),
+    "SIMP exponent p-1": (
+        "hmgref", "test_oracle",
+        "return Emin + rho ** penal * (E0 - Emin)", "return Emin + rho ** (penal - 1) * (E0 - Emin)"),
+    "sensitivity exponent p": (
+        "hmgref", "test_oracle",
+        "ds = penal * rho ** (penal - 1.0) * (E0 - Emin)", "ds = penal * rho ** penal * (E0 - Emin)"),
+    "strain energy of chi + u": (
+        "hmgref", "test_oracle", "d = chi[:, None, :] - ue", "d = chi[:, None, :] + ue"),
+    "OC without damping": (
+        "hmgref", "test_oracle", "return np.clip(x * B ** damp, lo, hi)", "return np.clip(x * B, lo, hi)"),
+    "stencil block transposed": (
+        "hmgref", "test_oracle", "A[3 * v + i, 3 * w + j]", "A[3 * v + j, 3 * w + i]"),
+    "stencil x/z offsets swapped": (
+        "hmgref", "test_oracle",
+        "d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)\n                w =",
+        "d = (dz + 1) + 3 * (dy + 1) + 9 * (dx + 1)\n                w ="),
+    # network oracle
+    "conv tap x/z swapped": (
+        "nnref", "test_nnref",
+        "((t % 3) - 1, ((t // 3) % 3) - 1, (t // 9) - 1)", "((t // 9) - 1, ((t // 3) % 3) - 1, (t % 3) - 1)"),
+    "conv shift sign": (
+        "nnref", "test_nnref",
+        "np.roll(x, shift=(-dz, -dy, -dx), axis=(-3, -2, -1))",
+        "np.roll(x, shift=(dz, dy, dx), axis=(-3, -2, -1))"),
+    "backward data shift sign": (
+        "nnref", "test_nnref",
+        "w[:, :, t], dz), -ddx, -ddy, -ddz)", "w[:, :, t], dz), ddx, ddy, ddz)"),
+    "pool backward over 4": (
+        "nnref", "test_nnref", "axis=3), 2, axis=4) / 8.0", "axis=3), 2, axis=4) / 4.0"),
+    "bf16 rounding ties away": (
+        "nnref", "test_nnref", "u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16",
+        "u = (u + 0x8000) >> 16 << 16"),
+}
+
+
+def _copy_tree(dst):
+    os.makedirs(os.path.join(dst, "tests"))
+    shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(dst, "oracle"),
+                    ignore=shutil.ignore_patterns("__pycache__"))
+    shutil.copytree(os.path.join(ROOT, "tests", "golden"), os.path.join(dst, "tests", "golden"))
+    for f in ("conftest.py", "test_oracle.py", "test_nnref.py"):
+        shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests", f))
+    os.makedirs(os.path.join(dst, "paper_2301_08911_amd"))
+    for f in ("__init__.py", "inputs.py"):
+        shutil.copy(os.path.join(ROOT, "paper_2301_08911_amd", f),
+                    os.path.join(dst, "paper_2301_08911_amd", f))
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_a_planted_mistake(name, tmp_path):
+    module, pins, original, planted = MUTATIONS[name]
+    dst = str(tmp_path / "tree")
+    _copy_tree(dst)
+    path = os.path.join(dst, "oracle", module + ".py")
+    src = open(path).read()
+    assert src.count(original) == 1, f"mutation site of {name!r} not found once in {module}.py"
+    with open(path, "w") as fh:
+        fh.write(src.replace(original, planted))
+    res = subprocess.run(
+        [sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+         os.path.join("tests", pins + ".py")],
+        cwd=dst, capture_output=True, text=True, timeout=600)
+    assert res.returncode == 1, (name, res.stdout[-2000:], res.stderr[-2000:])
+    assert "failed" in res.stdout
