@@ -11,6 +11,7 @@ SYMBOLS = (
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
     "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
     "hmg_load_vectors", "hmg_vcycle", "hmg_transfer", "hmg_profile", "hmg_profile_read",
+    "hmg_element_constants",
     "hmg_batch_create", "hmg_batch_destroy", "hmg_batch_set_density", "hmg_batch_tune",
     "hmg_batch_solve", "hmg_batch_elastic_tensors", "hmg_batch_last_error",
     # include/hmg_nn.h
@@ -68,6 +69,7 @@ def load() -> ctypes.CDLL:
         "hmg_num_levels": ([vp, P(i32)], i32),
         "hmg_level_dims": ([vp, i32, P(i32)], i32),
         "hmg_level_omega": ([vp, i32, P(f64)], i32),
+        "hmg_element_constants": ([f64, P(f64), P(f64)], i32),
         "hmg_apply_operator": ([vp, i32, vp, vp], i32),
         "hmg_get_stencil": ([vp, i32, vp], i32),
         "hmg_load_vectors": ([vp, vp], i32),

@@ -63,3 +63,34 @@ def test_no_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.0, 0.45, -0.5])
+def test_library_element_constants_match_the_oracle(nu):
+    """The library's K0 (exact 1D integrals) and load template against the
+    oracle's (2x2x2 Gauss quadrature); host-only, so it runs without a GPU."""
+    import numpy as np
+    from oracle import hmgref as O
+    from paper_2301_08911_amd import _lib
+    lib = _lib.load()
+    K0 = np.zeros(576)
+    load = np.zeros(144)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.hmg_element_constants(nu, K0.ctypes.data_as(dp), load.ctypes.data_as(dp))
+    assert st == 0
+    K0o = O.element_stiffness(1.0, nu)
+    assert np.abs(K0.reshape(24, 24) - K0o).max() < 1e-14 * np.abs(K0o).max()
+    ref = O.unit_strain_displacements() @ K0o            # (6, 24) = (K0 chi^i)^T
+    assert np.abs(load.reshape(6, 24) - ref).max() < 1e-14 * np.abs(K0o).max()
+
+
+def test_library_element_constants_refuse_bad_arguments():
+    import numpy as np
+    from paper_2301_08911_amd import _lib
+    lib = _lib.load()
+    K0 = np.zeros(576)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.hmg_element_constants(0.5, K0.ctypes.data_as(dp), None) == 1
+    assert lib.hmg_element_constants(-1.0, K0.ctypes.data_as(dp), None) == 1
+    assert lib.hmg_element_constants(0.3, None, None) == 1
+    assert lib.hmg_element_constants(0.3, K0.ctypes.data_as(dp), None) == 0
