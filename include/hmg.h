@@ -236,10 +236,12 @@ const char* hmg_batch_last_error(hmg_batch b);
  * unit-strain load template K0 chi^i of the six cases (Sec. 4.2,
  * Eq. (macro-strain)).  K0_out: host array of 24*24 doubles, row-major, dof
  * 3a+k of local node a = a0 + 2 a1 + 4 a2.  load_out: host array of 6*24
- * doubles, load_out[i*24 + 3a+k], or NULL.  Host-only: no device is touched, so
- * the call works without a GPU.  HMG_E_INVALID for a NULL K0_out or nu outside
- * (-1, 0.5). */
-hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out);
+ * doubles, load_out[i*24 + 3a+k], or NULL.  lam0_out: the largest eigenvalue
+ * of blockdiag(K0)^-1 K0 (3x3 node blocks), which bounds the spectrum of the
+ * level-0 block-Jacobi operator for any densities, or NULL.  Host-only: no
+ * device is touched, so the call works without a GPU.  HMG_E_INVALID for a
+ * NULL K0_out or nu outside (-1, 0.5). */
+hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out);
 
 /* Number of multigrid levels and the cells per axis of one level. */
 hmg_status hmg_num_levels(hmg_ctx ctx, int32_t* levels_out);

@@ -1616,13 +1616,14 @@ hmg_status hmg_profile_read(hmg_ctx ctx, int32_t kernel, int64_t* launches, doub
   return HMG_OK;
 }
 
-hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out) {
+hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out) {
   if (!K0_out || !(nu > -1.0 && nu < 0.5)) return HMG_E_INVALID;
   std::unique_ptr<ElementConsts> ec(new ElementConsts);
   char err[256] = {0};
   if (build_element_consts(nu, ec.get(), err, sizeof(err)) != 0) return HMG_E_INVALID;
   std::memcpy(K0_out, ec->K0, sizeof(ec->K0));
   if (load_out) std::memcpy(load_out, ec->load, sizeof(ec->load));
+  if (lam0_out) *lam0_out = ec->lam0;
   return HMG_OK;
 }
 

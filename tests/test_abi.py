@@ -76,12 +76,21 @@ def test_library_element_constants_match_the_oracle(nu):
     K0 = np.zeros(576)
     load = np.zeros(144)
     dp = ctypes.POINTER(ctypes.c_double)
-    st = lib.hmg_element_constants(nu, K0.ctypes.data_as(dp), load.ctypes.data_as(dp))
+    lam0 = ctypes.c_double()
+    st = lib.hmg_element_constants(nu, K0.ctypes.data_as(dp), load.ctypes.data_as(dp),
+                                   ctypes.byref(lam0))
     assert st == 0
     K0o = O.element_stiffness(1.0, nu)
     assert np.abs(K0.reshape(24, 24) - K0o).max() < 1e-14 * np.abs(K0o).max()
     ref = O.unit_strain_displacements() @ K0o            # (6, 24) = (K0 chi^i)^T
     assert np.abs(load.reshape(6, 24) - ref).max() < 1e-14 * np.abs(K0o).max()
+    # spectral bound: largest eigenvalue of K0 v = lambda blockdiag(K0) v
+    from scipy.linalg import eigh
+    Bd = np.zeros((24, 24))
+    for a in range(8):
+        Bd[3 * a:3 * a + 3, 3 * a:3 * a + 3] = K0o[3 * a:3 * a + 3, 3 * a:3 * a + 3]
+    lam = eigh(K0o, Bd, eigvals_only=True).max()
+    assert abs(lam0.value - lam) < 1e-6 * lam, (lam0.value, lam)
 
 
 def test_library_element_constants_refuse_bad_arguments():
@@ -90,7 +99,7 @@ def test_library_element_constants_refuse_bad_arguments():
     lib = _lib.load()
     K0 = np.zeros(576)
     dp = ctypes.POINTER(ctypes.c_double)
-    assert lib.hmg_element_constants(0.5, K0.ctypes.data_as(dp), None) == 1
-    assert lib.hmg_element_constants(-1.0, K0.ctypes.data_as(dp), None) == 1
-    assert lib.hmg_element_constants(0.3, None, None) == 1
-    assert lib.hmg_element_constants(0.3, K0.ctypes.data_as(dp), None) == 0
+    assert lib.hmg_element_constants(0.5, K0.ctypes.data_as(dp), None, None) == 1
+    assert lib.hmg_element_constants(-1.0, K0.ctypes.data_as(dp), None, None) == 1
+    assert lib.hmg_element_constants(0.3, None, None, None) == 1
+    assert lib.hmg_element_constants(0.3, K0.ctypes.data_as(dp), None, None) == 0
