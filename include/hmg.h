@@ -238,10 +238,16 @@ const char* hmg_batch_last_error(hmg_batch b);
  * 3a+k of local node a = a0 + 2 a1 + 4 a2.  load_out: host array of 6*24
  * doubles, load_out[i*24 + 3a+k], or NULL.  lam0_out: the largest eigenvalue
  * of blockdiag(K0)^-1 K0 (3x3 node blocks), which bounds the spectrum of the
- * level-0 block-Jacobi operator for any densities, or NULL.  Host-only: no
+ * level-0 block-Jacobi operator for any densities, or NULL.  msig_out: host
+ * array of 8*24*24 doubles, or NULL: for each sub-position sigma = s0 + 2 s1 +
+ * 4 s2 of a fine element inside a coarse element, W_sigma^T K0 W_sigma, where
+ * W_sigma interpolates the coarse element's nodes trilinearly to the fine
+ * element's nodes (the first coarse level is assembled from these, Sec. 4.2
+ * Eq. (st-level-2)); msig_out[(sigma*24 + 3A+p)*24 + 3B+q].  Host-only: no
  * device is touched, so the call works without a GPU.  HMG_E_INVALID for a
  * NULL K0_out or nu outside (-1, 0.5). */
-hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out);
+hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out,
+                                 double* msig_out);
 
 /* Number of multigrid levels and the cells per axis of one level. */
 hmg_status hmg_num_levels(hmg_ctx ctx, int32_t* levels_out);

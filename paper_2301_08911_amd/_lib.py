@@ -69,7 +69,7 @@ def load() -> ctypes.CDLL:
         "hmg_num_levels": ([vp, P(i32)], i32),
         "hmg_level_dims": ([vp, i32, P(i32)], i32),
         "hmg_level_omega": ([vp, i32, P(f64)], i32),
-        "hmg_element_constants": ([f64, P(f64), P(f64), P(f64)], i32),
+        "hmg_element_constants": ([f64, P(f64), P(f64), P(f64), P(f64)], i32),
         "hmg_apply_operator": ([vp, i32, vp, vp], i32),
         "hmg_get_stencil": ([vp, i32, vp], i32),
         "hmg_load_vectors": ([vp, vp], i32),

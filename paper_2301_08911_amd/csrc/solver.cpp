@@ -1616,7 +1616,8 @@ hmg_status hmg_profile_read(hmg_ctx ctx, int32_t kernel, int64_t* launches, doub
   return HMG_OK;
 }
 
-hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out) {
+hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, double* lam0_out,
+                                 double* msig_out) {
   if (!K0_out || !(nu > -1.0 && nu < 0.5)) return HMG_E_INVALID;
   std::unique_ptr<ElementConsts> ec(new ElementConsts);
   char err[256] = {0};
@@ -1624,6 +1625,7 @@ hmg_status hmg_element_constants(double nu, double* K0_out, double* load_out, do
   std::memcpy(K0_out, ec->K0, sizeof(ec->K0));
   if (load_out) std::memcpy(load_out, ec->load, sizeof(ec->load));
   if (lam0_out) *lam0_out = ec->lam0;
+  if (msig_out) std::memcpy(msig_out, ec->msig, sizeof(ec->msig));
   return HMG_OK;
 }
 

@@ -77,8 +77,9 @@ def test_library_element_constants_match_the_oracle(nu):
     load = np.zeros(144)
     dp = ctypes.POINTER(ctypes.c_double)
     lam0 = ctypes.c_double()
+    msig = np.zeros(8 * 576)
     st = lib.hmg_element_constants(nu, K0.ctypes.data_as(dp), load.ctypes.data_as(dp),
-                                   ctypes.byref(lam0))
+                                   ctypes.byref(lam0), msig.ctypes.data_as(dp))
     assert st == 0
     K0o = O.element_stiffness(1.0, nu)
     assert np.abs(K0.reshape(24, 24) - K0o).max() < 1e-14 * np.abs(K0o).max()
@@ -91,6 +92,24 @@ def test_library_element_constants_match_the_oracle(nu):
         Bd[3 * a:3 * a + 3, 3 * a:3 * a + 3] = K0o[3 * a:3 * a + 3, 3 * a:3 * a + 3]
     lam = eigh(K0o, Bd, eigvals_only=True).max()
     assert abs(lam0.value - lam) < 1e-6 * lam, (lam0.value, lam)
+    # sub-element Galerkin matrices: W_sigma read off the oracle's prolongation
+    # (fine 8^3 from coarse 4^3, coarse element at (1,1,1), no wrap), and their
+    # sum is the stiffness of the 2h element, 2 K0 in 3D
+    msig = msig.reshape(8, 24, 24)
+    P = O.prolongation((8, 8, 8)).tocsr()
+    scale = np.abs(K0o).max()
+    for sg in range(8):
+        s0, s1, s2 = sg & 1, (sg >> 1) & 1, (sg >> 2) & 1
+        W = np.zeros((8, 8))
+        for b in range(8):
+            fx, fy, fz = 2 + s0 + (b & 1), 2 + s1 + ((b >> 1) & 1), 2 + s2 + ((b >> 2) & 1)
+            for A in range(8):
+                cx, cy, cz = 1 + (A & 1), 1 + ((A >> 1) & 1), 1 + ((A >> 2) & 1)
+                W[b, A] = P[3 * (fx + 8 * (fy + 8 * fz)), 3 * (cx + 4 * (cy + 4 * cz))]
+        assert np.allclose(W.sum(axis=1), 1.0, atol=1e-15)
+        W3 = np.kron(W, np.eye(3))
+        assert np.abs(msig[sg] - W3.T @ K0o @ W3).max() < 1e-14 * scale, sg
+    assert np.abs(msig.sum(axis=0) - 2.0 * K0o).max() < 1e-14 * scale
 
 
 def test_library_element_constants_refuse_bad_arguments():
@@ -99,7 +118,7 @@ def test_library_element_constants_refuse_bad_arguments():
     lib = _lib.load()
     K0 = np.zeros(576)
     dp = ctypes.POINTER(ctypes.c_double)
-    assert lib.hmg_element_constants(0.5, K0.ctypes.data_as(dp), None, None) == 1
-    assert lib.hmg_element_constants(-1.0, K0.ctypes.data_as(dp), None, None) == 1
-    assert lib.hmg_element_constants(0.3, None, None, None) == 1
-    assert lib.hmg_element_constants(0.3, K0.ctypes.data_as(dp), None, None) == 0
+    assert lib.hmg_element_constants(0.5, K0.ctypes.data_as(dp), None, None, None) == 1
+    assert lib.hmg_element_constants(-1.0, K0.ctypes.data_as(dp), None, None, None) == 1
+    assert lib.hmg_element_constants(0.3, None, None, None, None) == 1
+    assert lib.hmg_element_constants(0.3, K0.ctypes.data_as(dp), None, None, None) == 0
