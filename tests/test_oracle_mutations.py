@@ -92,6 +92,7 @@ def test_pins_catch_a_planted_mistake(name, tmp_path):
     res = subprocess.run(
         [sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
          os.path.join("tests", pins + ".py")],
-        cwd=dst, capture_output=True, text=True, timeout=600)
+        cwd=dst, capture_output=True, text=True, timeout=600,
+        env=dict(os.environ, PYTHONPATH=dst, PYTEST_ADDOPTS=""))
     assert res.returncode == 1, (name, res.stdout[-2000:], res.stderr[-2000:])
     assert "failed" in res.stdout
