@@ -96,3 +96,16 @@ def test_pins_catch_a_planted_mistake(name, tmp_path):
         env=dict(os.environ, PYTHONPATH=dst, PYTEST_ADDOPTS=""))
     assert res.returncode == 1, (name, res.stdout[-2000:], res.stderr[-2000:])
     assert "failed" in res.stdout
+
+
+@pytest.mark.parametrize("pins", ["test_oracle", "test_nnref"])
+def test_unmutated_copy_passes(pins, tmp_path):
+    """Control: the copied tree passes as is, so a failure above is the mistake's."""
+    dst = str(tmp_path / "tree")
+    _copy_tree(dst)
+    res = subprocess.run(
+        [sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+         os.path.join("tests", pins + ".py")],
+        cwd=dst, capture_output=True, text=True, timeout=600,
+        env=dict(os.environ, PYTHONPATH=dst, PYTEST_ADDOPTS=""))
+    assert res.returncode == 0, (res.stdout[-2000:], res.stderr[-2000:])
