@@ -218,6 +218,18 @@ def test_laminate_golden_4cubed(K0, chi):
     assert np.abs(C - gold).max() < 1e-9
 
 
+def test_golden_laminate_file_is_its_generator_output():
+    # the stored values are the closed form in exact rational arithmetic,
+    # written by the committed generator beside the file
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_laminate_4", os.path.join(GOLDEN, "make_laminate_4.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    with open(os.path.join(GOLDEN, "laminate_4.txt")) as fh:
+        assert fh.read() == gen.text()
+
+
 @pytest.mark.parametrize("shape,profile", [((4, 6, 8), [0.2, 1, 1, 0.4, 0.9, 0.05, 0.6, 1.0]),
                                            ((6, 4, 6), [1e-3, 1, 0.5, 1, 1e-3, 0.3])])
 def test_laminate_closed_form_any_profile(K0, chi, shape, profile):
