@@ -267,21 +267,25 @@ def absolute_floor(s, E: float = 1.0, nu: float = 0.3) -> float:
 
 
 def pcg_solve(K: sp.csr_matrix, f: np.ndarray, tol: float = 1e-10, max_iter: int = 20000,
-              x0: np.ndarray | None = None, eps_abs: float = 0.0):
-    """Block-Jacobi preconditioned CG on the projected singular periodic system.
+              x0: np.ndarray | None = None, eps_abs: float = 0.0, prec=None):
+    """Preconditioned CG on the projected singular periodic system.
 
     ``f`` is (c, n, 3).  Each case runs its own CG.  A case is converged when
     the recomputed residual satisfies ||f - K x|| <= max(tol ||f||, eps_abs); a
     case with ||f|| <= eps_abs is solved by x = 0 with zero iterations.
+    ``prec`` maps a (c, n, 3) residual to the preconditioned one; the default is
+    3x3 block Jacobi.  The preconditioner only changes how fast the iteration
+    gets there: the stopping test is on the recomputed residual.
     Returns the zero-mean solution (c, n, 3), iteration counts and the final
     relative residuals ||f - K x|| / ||f|| (reported as 0 for trivial cases).
     """
     f = translation_projection(np.asarray(f, dtype=np.float64))
     c, n, _ = f.shape
-    Minv = block_jacobi_inverse(K)
+    if prec is None:
+        Minv = block_jacobi_inverse(K)
 
-    def prec(r):
-        return np.einsum("nij,cnj->cni", Minv, r)
+        def prec(r):
+            return np.einsum("nij,cnj->cni", Minv, r)
 
     def matvec(v):
         return (K @ v.reshape(c, 3 * n).T).T.reshape(c, n, 3)
@@ -326,14 +330,142 @@ def pcg_solve(K: sp.csr_matrix, f: np.ndarray, tol: float = 1e-10, max_iter: int
 
 
 def solve_cases(s, shape, E: float = 1.0, nu: float = 0.3, tol: float = 1e-10,
-                max_iter: int = 20000, x0=None):
-    """Assemble K and the six loads for scale ``s`` and solve them (6, n, 3)."""
+                max_iter: int = 20000, x0=None, multigrid: bool = False):
+    """Assemble K and the six loads for scale ``s`` and solve them (6, n, 3).
+
+    ``multigrid`` preconditions CG with ``multigrid_preconditioner`` instead of
+    block Jacobi (same stopping test, so the same answer to the tolerance)."""
     K0 = element_stiffness(E, nu)
     chi = unit_strain_displacements()
     K = assemble_stiffness(s, shape, K0)
     f = load_vectors(s, shape, K0, chi)
+    prec = multigrid_preconditioner(K, shape) if multigrid else None
     return pcg_solve(K, f, tol=tol, max_iter=max_iter, x0=x0,
-                     eps_abs=absolute_floor(s, E, nu))
+                     eps_abs=absolute_floor(s, E, nu), prec=prec)
+
+
+def vertex_colours(shape) -> np.ndarray:
+    """Colour (x mod 2) + 2 (y mod 2) + 4 (z mod 2) of every vertex (Sec. 4.1,
+    the eight independent vertex subsets of the Gauss-Seidel relaxation)."""
+    nx, ny, nz = shape
+    v = np.arange(nx * ny * nz)
+    return (v % nx) % 2 + 2 * (((v // nx) % ny) % 2) + 4 * ((v // (nx * ny)) % 2)
+
+
+def gs_colour_step(K_rows: sp.csr_matrix, Dinv_rows: np.ndarray, r: np.ndarray, z: np.ndarray,
+                   verts: np.ndarray) -> np.ndarray:
+    """One colour of block Gauss-Seidel (Sec. 4.2, Eq. st-gs-relx), in place.
+
+    At the vertices ``verts`` of one colour, S_v u_v = f_v - M_v with M_v the
+    row sum without the diagonal block S_v, i.e. u_v += S_v^-1 (f - K u)_v.
+    ``K_rows`` holds the rows of K at those vertices (3 per vertex),
+    ``Dinv_rows`` the inverse diagonal blocks S_v^-1 there, r and z are
+    (c, n, 3).  Returns z."""
+    c, m, _ = z.shape
+    kz = (K_rows @ z.reshape(c, 3 * m).T).T.reshape(c, verts.size, 3)
+    z[:, verts] += np.einsum("nij,cnj->cni", Dinv_rows, r[:, verts] - kz)
+    return z
+
+
+def multigrid_preconditioner(K: sp.csr_matrix, shape, min_dim: int = 4, sweeps: int = 1,
+                             smoother: str = "gs", omega_scale: float = 1.0 / 1.1):
+    """One symmetric multigrid V-cycle (Sec. 3.3, Alg. 1) as a CG preconditioner.
+
+    Levels: K_{l+1} = P_l^T K_l P_l with the periodic trilinear P of
+    ``prolongation`` (restriction = P^T), halving while every axis stays even
+    and the coarse grid keeps at least ``min_dim`` cells per axis.  Coarsest
+    level: the dense solve of the vertex-0-pinned matrix.  Every residual is
+    projected to zero mean per component before it is smoothed or solved (the
+    translation null space); the cycle starts from zero on every level.
+
+    Smoothers (``sweeps`` before and after the coarse correction):
+      "gs": eight-colour block Gauss-Seidel (Sec. 4.2, Eq. st-gs-relx): for each
+            colour in turn, u_v += S_v^-1 (f - K u)_v at the vertices of that
+            colour, S_v the 3x3 diagonal block; colours 0..7 before the coarse
+            correction and 7..0 after it, so the cycle is symmetric.
+      "jacobi": damped 3x3 block Jacobi with damping omega_scale / lambda_l,
+            lambda_l the largest eigenvalue of D_l^-1 K_l estimated by 30
+            power iterations.
+    Both make the cycle symmetric positive definite on zero-mean fields.
+    Returns a function of a (c, n, 3) residual."""
+    Ks, shapes, Ps = [K.tocsr()], [tuple(shape)], []
+    while True:
+        nx, ny, nz = shapes[-1]
+        if nx % 2 or ny % 2 or nz % 2 or min(nx, ny, nz) // 2 < min_dim:
+            break
+        P = prolongation(shapes[-1])
+        Ps.append(P)
+        Ks.append((P.T @ Ks[-1] @ P).tocsr())
+        shapes.append((nx // 2, ny // 2, nz // 2))
+    L = len(Ks) - 1
+    Dinv, omegas, colour_rows = [], [], []
+    rng = np.random.default_rng(12345)
+    for l in range(L):
+        Kl = Ks[l]
+        Di = block_jacobi_inverse(Kl)
+        Dinv.append(Di)
+        if smoother == "jacobi":
+            m = Kl.shape[0] // 3
+            v = translation_projection(rng.standard_normal((m, 3)))
+            lam = 1.0
+            for _ in range(30):
+                w = np.einsum("nij,nj->ni", Di, (Kl @ v.ravel()).reshape(m, 3))
+                lam = float(np.linalg.norm(w) / np.linalg.norm(v))
+                v = translation_projection(w / np.linalg.norm(w))
+            omegas.append(omega_scale / lam)
+        elif smoother == "gs":
+            col = vertex_colours(shapes[l])
+            rows = []
+            for c in range(8):
+                verts = np.flatnonzero(col == c)
+                dofs = (3 * verts[:, None] + np.arange(3)[None, :]).ravel()
+                rows.append((verts, Kl[dofs, :].tocsr()))
+            colour_rows.append(rows)
+        else:
+            raise ValueError(smoother)
+    Kc = Ks[-1].toarray()
+    Kc[0:3, :] = 0.0
+    Kc[:, 0:3] = 0.0
+    Kc[0:3, 0:3] = np.eye(3)
+    Kc_inv = np.linalg.inv(Kc)
+
+    def apply(Kl, v):
+        c, m, _ = v.shape
+        return (Kl @ v.reshape(c, 3 * m).T).T.reshape(c, m, 3)
+
+    def smooth(l, r, z, order):
+        if smoother == "jacobi":
+            return z + omegas[l] * np.einsum("nij,cnj->cni", Dinv[l], r - apply(Ks[l], z))
+        for col in order:
+            verts, Kcol = colour_rows[l][col]
+            z = gs_colour_step(Kcol, Dinv[l][verts], r, z, verts)
+        return z
+
+    def cycle(l, r):
+        r = translation_projection(r)
+        if l == L:
+            c, m, _ = r.shape
+            rhs = r.reshape(c, 3 * m).T.copy()
+            rhs[0:3, :] = 0.0
+            return translation_projection((Kc_inv @ rhs).T.reshape(c, m, 3))
+        z = np.zeros_like(r)
+        for _ in range(sweeps):
+            z = smooth(l, r, z, range(8))
+        P = Ps[l]
+        t = r - apply(Ks[l], z)
+        c, m, _ = t.shape
+        rc = (P.T @ t.reshape(c, 3 * m).T).T.reshape(c, -1, 3)
+        ec = cycle(l + 1, rc)
+        z = z + (P @ ec.reshape(c, -1).T).T.reshape(c, m, 3)
+        for _ in range(sweeps):
+            z = smooth(l, r, z, range(7, -1, -1))
+        return z
+
+    def prec(r):
+        return cycle(0, np.asarray(r, dtype=np.float64))
+
+    prec.levels = L + 1
+    return prec
 
 
 def dense_pinned_solve(K: sp.spmatrix, f: np.ndarray) -> np.ndarray:
@@ -487,6 +619,30 @@ def prolongation(shape) -> sp.csr_matrix:
                                 cols.append(3 * V + k)
                                 vals.append(wx * wy * wz)
     return sp.csr_matrix((vals, (rows, cols)), shape=(3 * nx * ny * nz, 3 * cx * cy * cz))
+
+
+def prolongate(uc: np.ndarray, shape) -> np.ndarray:
+    """P uc without forming P: periodic trilinear interpolation of a (c, n_c, 3)
+    coarse field on the (n/2)^3 grid to the fine grid ``shape`` (x fastest).
+
+    Fine vertex 2X along an axis takes coarse X; fine 2X + 1 takes the mean of
+    coarse X and X + 1 (periodic), one axis after the other."""
+    nx, ny, nz = shape
+    c = uc.shape[0]
+    U = np.asarray(uc, dtype=np.float64).reshape(c, nz // 2, ny // 2, nx // 2, 3)
+    for axis, nf in ((3, nx), (2, ny), (1, nz)):
+        odd = 0.5 * (U + np.roll(U, -1, axis=axis))
+        shp = list(U.shape)
+        shp[axis] = nf
+        out = np.empty(shp)
+        sl_even = [slice(None)] * 5
+        sl_odd = [slice(None)] * 5
+        sl_even[axis] = slice(0, nf, 2)
+        sl_odd[axis] = slice(1, nf, 2)
+        out[tuple(sl_even)] = U
+        out[tuple(sl_odd)] = odd
+        U = out
+    return U.reshape(c, nx * ny * nz, 3)
 
 
 def stencil_blocks(A: sp.spmatrix, shape) -> np.ndarray:

@@ -126,7 +126,8 @@ class UNetRef:
         return w, p[self.boff[k]:self.boff[k] + co]
 
     def forward(self, p, x):
-        """Returns y and the cache needed by backward."""
+        """Returns y and the cache needed by backward; cache[("pre", k)] holds
+        the pre-activation of ReLU layer k."""
         L = self.levels
         cache = {"x": x}
         k = 0
@@ -136,23 +137,31 @@ class UNetRef:
             if l >= 1:
                 h = pool2(skips[-1])
                 cache[("pool", l)] = h
-            w, b = self.unpack(p, k); k += 1
-            a = np.maximum(conv3d(self.R(h), self.R(w), b), 0.0)
+            w, b = self.unpack(p, k)
+            cache[("pre", k)] = conv3d(self.R(h), self.R(w), b)
+            a = np.maximum(cache[("pre", k)], 0.0)
+            k += 1
             cache[("enc_in", l)] = h
             cache[("enc_a", l)] = a
-            w, b = self.unpack(p, k); k += 1
-            s = np.maximum(conv3d(self.R(a), self.R(w), b), 0.0)
+            w, b = self.unpack(p, k)
+            cache[("pre", k)] = conv3d(self.R(a), self.R(w), b)
+            s = np.maximum(cache[("pre", k)], 0.0)
+            k += 1
             cache[("skip", l)] = s
             skips.append(s)
         src = skips[-1]
         for l in range(L - 2, -1, -1):
             cat = np.concatenate([up2(src), skips[l]], axis=1)
             cache[("cat", l)] = cat
-            w, b = self.unpack(p, k); k += 1
-            da = np.maximum(conv3d(self.R(cat), self.R(w), b), 0.0)
+            w, b = self.unpack(p, k)
+            cache[("pre", k)] = conv3d(self.R(cat), self.R(w), b)
+            da = np.maximum(cache[("pre", k)], 0.0)
+            k += 1
             cache[("dec_a", l)] = da
-            w, b = self.unpack(p, k); k += 1
-            db = np.maximum(conv3d(self.R(da), self.R(w), b), 0.0)
+            w, b = self.unpack(p, k)
+            cache[("pre", k)] = conv3d(self.R(da), self.R(w), b)
+            db = np.maximum(cache[("pre", k)], 0.0)
+            k += 1
             cache[("dec_b", l)] = db
             src = db
         cache["top"] = src

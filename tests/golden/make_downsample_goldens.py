@@ -1,0 +1,146 @@
+"""Write the oracle's results for the box-downsampled benchmark densities.
+
+Run from the repository root:  python tests/golden/make_downsample_goldens.py [name ...]
+
+Only the FP64 oracle (``oracle.hmgref``) and the seeded input generators
+(``paper_2301_08911_amd.inputs``, which hold none of the method's arithmetic)
+are used.  Each output file records its recipe, the oracle's PCG iterations
+and recomputed relative residuals (stopping test 1e-10), the 6x6 C^H (Sec.
+3.2, Eq. elasttensor), and, for the optimization leg, the shear-objective
+sensitivity and one OC update at sampled elements.
+
+* ``shear128_ds32.txt``: the 128^3 smoothed-noise design (sigma 3, VF 0.2,
+  seed 1) box-averaged to 32^3, filtered (radius 2), first optimization
+  iteration of the shear objective F = -(C33+C44+C55)/3: C^H, dF/drho~ and
+  dF/dx = H dF/drho~ at every 97th element, and the OC update (volume 0.2,
+  move 0.05, damping 0.5, xmin 1e-3) of the downsampled design.
+* ``vf015_256_ds32.txt``: the 256^3 smoothed-noise density (sigma 3,
+  VF 0.15, seed 2) box-averaged to 32^3: C^H.
+* ``batch_small_cells.txt``: C^H of the cells of at most 24^3 vertices among
+  the six uneven cells of the batched-solve test (smoothed noise, sigma 2,
+  seed 40 + k, VF 0.15 + 0.05 k for cell k).
+
+The VF 0.15 density is box-averaged by 8 (to 32^3), not by 4 (to 64^3): a
+factor-4 average of a sigma-3 field keeps near-binary, near-percolating
+voxels, on which the oracle's multigrid-preconditioned CG needs about eight
+times more iterations per doubling of the resolution (about 600 at 16^3 and
+8000 at 32^3 for such fields), which puts a 64^3 solve to 1e-10 at days of
+host time.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import hmgref as O  # noqa: E402
+from paper_2301_08911_amd import inputs as I  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SAMPLE_STRIDE = 97
+
+
+def _solve(rho, shape, log):
+    s = O.simp_scale(rho)
+    K0 = O.element_stiffness()
+    chi = O.unit_strain_displacements()
+    K = O.assemble_stiffness(s, shape, K0)
+    f = O.load_vectors(s, shape, K0, chi)
+    prec = O.multigrid_preconditioner(K, shape, smoother="gs")
+    t = time.time()
+    u, it, rr = O.pcg_solve(K, f, tol=1e-10, max_iter=200000, eps_abs=O.absolute_floor(s),
+                            prec=prec)
+    log(f"  solved in {time.time() - t:.0f} s, iterations {it.tolist()}, relres {rr.max():.2e}")
+    C = O.elastic_tensor(s, u, shape, K0, chi)
+    return u, it, rr, C, K0, chi
+
+
+def _fmt(name, a):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    return f"{name} {a.size} " + " ".join(f"{v:.17g}" for v in a) + "\n"
+
+
+def shear128_ds32(log):
+    shape = (32, 32, 32)
+    x_fine = I.smoothed_noise_density((128, 128, 128), 1, 0.2, sigma=3.0)
+    x = I.box_downsample(x_fine, 4).ravel().astype(np.float32).astype(np.float64)
+    rho = O.density_filter(x, shape, 2.0).astype(np.float32).astype(np.float64)
+    u, it, rr, C, K0, chi = _solve(rho, shape, log)
+    W = O.shear_weights()
+    g = O.sensitivity(rho, u, shape, K0, chi, W)
+    gx = O.density_filter(g, shape, 2.0)
+    xnew, lam = O.oc_update(x, gx, 0.2, 0.05, 0.5, 1e-3)
+    idx = np.arange(0, x.size, SAMPLE_STRIDE)
+    head = ("# shear128_ds32: 128^3 smoothed noise (seed 1, sigma 3, VF 0.2) box mean 4 -> 32^3,\n"
+            "# x rounded to float32; rho~ = H x (radius 2) rounded to float32; FP64 oracle,\n"
+            "# multigrid-preconditioned CG to a recomputed relative residual 1e-10.\n"
+            f"# sampled elements: every {SAMPLE_STRIDE}th index from 0\n")
+    body = (_fmt("iters", it) + _fmt("relres", rr) + _fmt("C", C) + _fmt("dfdrho_sum", g.sum())
+            + _fmt("dfdrho", g[idx]) + _fmt("dfdx", gx[idx]) + _fmt("lambda", lam)
+            + _fmt("xnew", xnew[idx]) + _fmt("xnew_mean", xnew.mean()))
+    return head + body
+
+
+def vf015_256_ds32(log):
+    shape = (32, 32, 32)
+    rho_fine = I.smoothed_noise_density((256, 256, 256), 2, 0.15, sigma=3.0)
+    rho = I.box_downsample(rho_fine, 8).ravel().astype(np.float32).astype(np.float64)
+    u, it, rr, C, _, _ = _solve(rho, shape, log)
+    head = ("# vf015_256_ds32: 256^3 smoothed noise (seed 2, sigma 3, VF 0.15) box mean 8 -> 32^3,\n"
+            "# rounded to float32; FP64 oracle, multigrid-preconditioned CG to a recomputed\n"
+            "# relative residual 1e-10.\n")
+    return head + _fmt("iters", it) + _fmt("relres", rr) + _fmt("C", C)
+
+
+BATCH_SHAPES = [(32, 32, 32), (16, 16, 16), (24, 24, 24), (16, 24, 8), (48, 48, 48), (16, 16, 16)]
+
+
+def batch_small_cells(log):
+    out = ("# batch_small_cells: cell k of shape BATCH_SHAPES[k] (x, y, z), smoothed noise\n"
+           "# (seed 40 + k, sigma 2, VF 0.15 + 0.05 k) rounded to float32; FP64 oracle,\n"
+           "# multigrid-preconditioned CG to a recomputed relative residual 1e-10.\n")
+    for k, shape in enumerate(BATCH_SHAPES):
+        if np.prod(shape) > 24 ** 3:
+            continue
+        rho = I.smoothed_noise_density(shape, 40 + k, 0.15 + 0.05 * k, sigma=2.0)
+        rho = rho.astype(np.float32).astype(np.float64).ravel()
+        log(f"cell {k} {shape}")
+        _, it, rr, C, _, _ = _solve(rho, shape, log)
+        out += _fmt(f"iters{k}", it) + _fmt(f"C{k}", C)
+    return out
+
+
+GOLDENS = {"shear128_ds32": shear128_ds32, "vf015_256_ds32": vf015_256_ds32,
+           "batch_small_cells": batch_small_cells}
+
+
+def read_golden(path):
+    """Parse a golden file into {name: float64 array}."""
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            out[parts[0]] = np.array([float(v) for v in parts[2:]])
+    return out
+
+
+def main(names):
+    for name in names or GOLDENS:
+        def log(msg, name=name):
+            print(f"[{name}] {msg}", flush=True)
+        log("start")
+        text = GOLDENS[name](log)
+        with open(os.path.join(HERE, name + ".txt"), "w") as fh:
+            fh.write(text)
+        log("written")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -518,3 +518,100 @@ def test_splitmix64_reference_vector():
     # SplitMix64 with state 0: first output of the published generator
     # (state += golden gamma, then mix) is 0xE220A8397B1DCDAF.
     assert int(I.splitmix64(np.array([0], dtype=np.uint64))[0]) == 0xE220A8397B1DCDAF
+
+
+# --------------------------------------------------------------------- multigrid oracle
+
+def test_vertex_colours_are_independent_sets():
+    # eight colours of equal size; no vertex shares its colour with any of its
+    # 26 neighbours on an even periodic grid (Sec. 4.1 subsets)
+    shape = (8, 6, 4)
+    col = O.vertex_colours(shape)
+    n = col.size
+    assert sorted(np.bincount(col).tolist()) == [n // 8] * 8
+    nx, ny, nz = shape
+    v = np.arange(n)
+    x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+    for dx, dy, dz in itertools.product((-1, 0, 1), repeat=3):
+        if (dx, dy, dz) == (0, 0, 0):
+            continue
+        w = (x + dx) % nx + nx * (((y + dy) % ny) + ny * ((z + dz) % nz))
+        assert (col[w] != col).all(), (dx, dy, dz)
+
+
+def test_gs_colour_step_solves_its_block_rows(K0):
+    # after the step, the residual vanishes at the updated vertices
+    shape = (6, 6, 6)
+    s = O.simp_scale(I.uniform01(3, 1, 216) + 0.05)
+    K = O.assemble_stiffness(s, shape, K0)
+    Dinv = O.block_jacobi_inverse(K)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal((2, 216, 3))
+    z = rng.standard_normal((2, 216, 3))
+    col = O.vertex_colours(shape)
+    for c in (0, 5):
+        verts = np.flatnonzero(col == c)
+        dofs = (3 * verts[:, None] + np.arange(3)[None, :]).ravel()
+        z = O.gs_colour_step(K[dofs, :].tocsr(), Dinv[verts], r, z, verts)
+        res = r - (K @ z.reshape(2, -1).T).T.reshape(2, 216, 3)
+        assert np.abs(res[:, verts]).max() < 1e-12 * np.abs(r).max()
+        assert np.abs(res).max() > 1e-3  # the other colours are untouched
+
+
+@pytest.mark.parametrize("smoother", ["gs", "jacobi"])
+def test_multigrid_preconditioner_symmetric_positive(K0, smoother):
+    shape = (8, 8, 8)
+    s = O.simp_scale(I.smoothed_noise_density(shape, 6, 0.3, sigma=1.0))
+    K = O.assemble_stiffness(s, shape, K0)
+    M = O.multigrid_preconditioner(K, shape, smoother=smoother)
+    assert M.levels == 2
+    rng = np.random.default_rng(7)
+    a = O.translation_projection(rng.standard_normal((6, 512, 3)))
+    b = O.translation_projection(rng.standard_normal((6, 512, 3)))
+    Ma, Mb = M(a), M(b)
+    for c in range(6):
+        x, y = float((Ma[c] * b[c]).sum()), float((a[c] * Mb[c]).sum())
+        assert abs(x - y) <= 1e-12 * max(abs(x), abs(y))
+        assert float((Ma[c] * a[c]).sum()) > 0
+
+
+@pytest.mark.parametrize("smoother", ["gs", "jacobi"])
+def test_multigrid_pcg_matches_brute_force(K0, chi, smoother):
+    # the preconditioner changes only the path: the solution is the dense one
+    shape = (8, 8, 8)
+    rho = I.smoothed_noise_density(shape, 8, 0.35, sigma=1.2)
+    s = O.simp_scale(rho)
+    K = O.assemble_stiffness(s, shape, K0)
+    f = O.translation_projection(O.load_vectors(s, shape, K0, chi))
+    prec = O.multigrid_preconditioner(K, shape, smoother=smoother)
+    u, it, rr = O.pcg_solve(K, f, eps_abs=O.absolute_floor(s), prec=prec)
+    assert (rr <= 1e-10).all()
+    ud = O.dense_pinned_solve(K, f)
+    assert np.abs(u - ud).max() < 1e-8 * np.abs(ud).max()
+
+
+def test_voigt_reuss_bounds_are_laminate_extremes():
+    # a z-laminate attains the Voigt bound in in-plane shear (C33 = <s> mu)
+    # and the Reuss bound in out-of-plane shear (C44 = C55 = <1/s>^-1 mu)
+    prof = np.array([1.0, 0.2, 0.6, 1e-3, 0.9, 0.35])
+    s_prof = O.simp_scale(prof)
+    ref = _laminate_closed_form(s_prof, LAM, MU, 0.3)
+    s = np.repeat(s_prof, 4 * 4)
+    V, R = O.voigt_bound(s), O.reuss_bound(s)
+    assert abs(V[3, 3] - ref[3, 3]) < 1e-14 * ref[3, 3]
+    assert abs(R[4, 4] - ref[4, 4]) < 1e-14 * ref[4, 4]
+    assert abs(R[5, 5] - ref[5, 5]) < 1e-14 * ref[5, 5]
+    # both are the base tensor scaled: Voigt by <s>, Reuss by <1/s>^-1
+    D = O.constitutive_matrix()
+    assert np.abs(V / V[0, 0] - D / D[0, 0]).max() < 1e-15
+    assert np.abs(R / R[0, 0] - D / D[0, 0]).max() < 1e-15
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (8, 12, 16)])
+def test_prolongate_equals_sparse_P(shape):
+    # two independent implementations of the trilinear P
+    nc = (shape[0] // 2) * (shape[1] // 2) * (shape[2] // 2)
+    uc = np.random.default_rng(9).standard_normal((2, nc, 3))
+    P = O.prolongation(shape)
+    ref = (P @ uc.reshape(2, -1).T).T.reshape(2, -1, 3)
+    assert np.abs(O.prolongate(uc, shape) - ref).max() < 1e-15

@@ -47,6 +47,18 @@ MUTATIONS = {
         "hmgref", "test_oracle",
         "d = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)\n                w =",
         "d = (dz + 1) + 3 * (dy + 1) + 9 * (dx + 1)\n                w ="),
+    "colour y bit dropped": (
+        "hmgref", "test_oracle",
+        "(v % nx) % 2 + 2 * (((v // nx) % ny) % 2)", "(v % nx) % 2 + 0 * (((v // nx) % ny) % 2)"),
+    "Gauss-Seidel step sign": (
+        "hmgref", "test_oracle", 'Dinv_rows, r[:, verts] - kz)', 'Dinv_rows, r[:, verts] + kz)'),
+    "Reuss bound from <s>": (
+        "hmgref", "test_oracle",
+        "return constitutive_matrix(E, nu) / float(np.mean(1.0 / np.asarray(s)))",
+        "return constitutive_matrix(E, nu) * float(np.mean(np.asarray(s)))"),
+    "prolongate odd weight": (
+        "hmgref", "test_oracle", "odd = 0.5 * (U + np.roll(U, -1, axis=axis))",
+        "odd = 0.5 * (U + np.roll(U, 1, axis=axis))"),
     # network oracle
     "conv tap x/z swapped": (
         "nnref", "test_nnref",
