@@ -17,12 +17,15 @@ solve wall time); s_per_opt_iter is reported beside it.  --forms adds the
 other forms of the method on the same cell (each gets its own warm-up and
 steps): mixed_bf16 (bf16 multigrid vectors), mixed_bf16_stencil (also bf16
 coarse stencils), learned (network warm start with the cold start as
-fallback), cold (zero start every step).  The roofline object
+fallback), cold (zero start every step).  By default the line carries plain
+(headline), mixed_bf16, cold and learned; every form starts from the same design,
+and its first-step C^H is compared with the headline form's.  The roofline object
 covers the level-0 kernel with the largest share of the timed solve time of the
 first form, timed with HIP events on the context stream; its HBM traffic comes
 from the committed rocprofv3 counter summary when that summary was taken on the
 same kernel source.  The CPU baseline times the FP64 oracle on a bounded
-sample.  --workload batch48 runs the batched form instead: 48 cells with sizes
+sample (the 64^3 box-downsample, 20 PCG iterations per load case, the six cases in
+parallel worker processes).  --workload batch48 runs the batched form instead: 48 cells with sizes
 drawn from {32, 48, 64, 96, 128}^3 in lockstep.
 """
 from __future__ import annotations
@@ -111,8 +114,25 @@ def copy_bandwidth(nbytes=1 << 31, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def _oracle_case_worker(args):
+    """One load case of the oracle's FP64 block-Jacobi CG (runs in a worker process)."""
+    K, f_case, iters = args
+    from oracle import hmgref as O
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:  # pragma: no cover
+        pass
+    t0 = time.perf_counter()
+    _, it, _ = O.pcg_solve(K, f_case, tol=1e-30, max_iter=iters, eps_abs=0.0)
+    return int(it.sum()), time.perf_counter() - t0
+
+
 def cpu_baseline(rho_full, n_full: int, sample: int, iters: int) -> dict:
-    """FP64 oracle (CSR + block-Jacobi CG) timed on the host for `iters` PCG iterations."""
+    """FP64 oracle (CSR + block-Jacobi CG) timed on the host cores: the six load
+    cases of the box-downsampled cell run as six worker processes, `iters` PCG
+    iterations each.  Called before the GPU is touched (the workers are forked)."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import hmgref as O
     from paper_2301_08911_amd import inputs as I
@@ -123,24 +143,24 @@ def cpu_baseline(rho_full, n_full: int, sample: int, iters: int) -> dict:
     s = O.simp_scale(rho)
     K = O.assemble_stiffness(s, shape, K0)
     f = O.load_vectors(s, shape, K0, chi)
-    try:
-        from threadpoolctl import threadpool_limits
-        limit = threadpool_limits(1)
-    except ImportError:  # pragma: no cover
-        limit = None
+    workers = max(1, min(6, os.cpu_count() or 1))
+    jobs = [(K, f[c:c + 1], iters) for c in range(6)]
     t0 = time.perf_counter()
-    _, it, _ = O.pcg_solve(K, f, tol=1e-30, max_iter=iters, eps_abs=0.0)
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_case_worker, jobs, chunksize=1)
     dt = time.perf_counter() - t0
-    if limit is not None:
-        limit.restore_original_limits()
-    dofit = float(np.sum(it)) * 3 * sample ** 3
-    return {"value": dofit / dt, "unit": "DOF-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}^3 box-downsample of the benchmark cell, {iters} block-Jacobi PCG "
-                      f"iterations x 6 cases in FP64 (scipy CSR, one thread); {dt:.1f} s"}
+    dofit = float(sum(r[0] for r in res)) * 3 * sample ** 3
+    return {"value": dofit / dt, "unit": "DOF-iters/s", "cores": workers, "kind": "oracle",
+            "sample": f"{sample}^3 box-downsample of the benchmark cell, {iters} block-Jacobi "
+                      f"PCG iterations per load case in FP64 (scipy CSR), the six cases in "
+                      f"{workers} worker processes of one thread each; {dt:.1f} s wall"}
 
 
-def run_form(form, x0_host, n, args, W, profile):
-    """Warm-up and timed optimization steps of one form; returns its record."""
+def run_form(form, x0_host, n, args, W, profile, warmup, steps):
+    """Warm-up and timed optimization steps of one form; returns its record.
+
+    Every form starts from the same design x0, so the C^H of its first step
+    (whether warm-up or timed) is comparable across forms."""
     import numpy as np
     import torch
     from paper_2301_08911_amd.hmg import Context
@@ -155,6 +175,7 @@ def run_form(form, x0_host, n, args, W, profile):
         net = nn.Net()
         net.load(os.path.join(ROOT, "paper_2301_08911_amd", "weights", "warmstart_l4c8.npy"))
     guesses = []
+    C_first = []
 
     def opt_step(first):
         ctx.filter(x, out=rho, radius=2.0)
@@ -174,9 +195,11 @@ def run_form(form, x0_host, n, args, W, profile):
         ctx.sensitivity(W, out=g)
         ctx.filter(g, out=gx, radius=2.0, adjoint=True)
         ctx.oc_update(x, gx, 0.3, 0.05, 0.5, 1e-3)
+        if not C_first:
+            C_first.append(C)
         return res, ts, C
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         res, ts, C = opt_step(w == 0)
         log(f"{form} warmup {w}: iters {res.iters.tolist()} solve {ts:.3f} s B {bulk_modulus(C):.6f}")
     torch.cuda.synchronize()
@@ -184,8 +207,8 @@ def run_form(form, x0_host, n, args, W, profile):
         ctx.profile(True)
     total_dofit, solve_s, iters_all, relres_max, Bs = 0.0, 0.0, [], 0.0, []
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        res, ts, C = opt_step(args.warmup == 0 and k == 0)
+    for k in range(steps):
+        res, ts, C = opt_step(warmup == 0 and k == 0)
         total_dofit += float(res.iters.sum()) * 3 * ctx.n
         solve_s += ts
         iters_all.append(res.iters.tolist())
@@ -196,9 +219,14 @@ def run_form(form, x0_host, n, args, W, profile):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     rec = {"dof_iters_per_s": total_dofit / solve_s if solve_s > 0 else 0.0,
-           "s_per_opt_iter": elapsed / args.steps, "solve_s_per_opt_iter": solve_s / args.steps,
+           "s_per_opt_iter": elapsed / steps, "solve_s_per_opt_iter": solve_s / steps,
            "pcg_iters": iters_all, "max_relres": relres_max, "bulk_modulus": Bs,
-           "precision": prec}
+           "precision": prec, "warmup": warmup, "steps": steps,
+           "start": {"plain": "previous iterate (zero on the first step)",
+                     "mixed_bf16": "previous iterate (zero on the first step)",
+                     "mixed_bf16_stencil": "previous iterate (zero on the first step)",
+                     "cold": "zero", "learned": "network guess, zero if rejected"}[form],
+           "C_first": C_first[0].tolist()}
     if guesses:
         rec["warm_start_relres_used"] = guesses
     prof = ctx.profile_read() if profile else None
@@ -267,9 +295,12 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
-    ap.add_argument("--forms", default="plain",
+    ap.add_argument("--forms", default="plain,mixed_bf16,cold,learned",
                     help="comma list of plain, mixed_bf16, mixed_bf16_stencil, learned, cold "
-                         "(the first is the headline)")
+                         "(the first is the headline and runs --warmup + --steps steps; the "
+                         "others run --form-steps timed steps after one warm-up step, none for "
+                         "cold and learned, whose every step starts without the previous iterate)")
+    ap.add_argument("--form-steps", type=int, default=1)
     ap.add_argument("--workload", default="cell", choices=["cell", "batch48"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=3000)
@@ -280,31 +311,50 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (multi-GPU "
               "sharding is a design, not built)", file=sys.stderr)
         sys.exit(2)
+    t_start = time.perf_counter()
     if args.workload == "batch48":
         print(json.dumps(bench_batch(args)), flush=True)
         return
 
     import numpy as np
-    import torch
     from paper_2301_08911_amd import inputs as I
 
-    torch.cuda.set_device(0)
-    copy_gbs = copy_bandwidth()
-    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     n = args.n
     sigma = 3.0 * n / 64.0
     log(f"generating {n}^3 smoothed-noise cell (sigma {sigma:g}, VF 0.3)")
     t = time.perf_counter()
     x_host = I.smoothed_noise_density((n, n, n), args.seed, 0.3, sigma=sigma)
     log(f"  done in {time.perf_counter() - t:.1f} s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before any GPU use: the oracle's worker processes are forked
+        log("timing the CPU oracle baseline")
+        sample = 64 if n % 64 == 0 else n
+        cpu = cpu_baseline(x_host, n, sample, 20)
+        log(f"  {cpu['value']:.3e} DOF-iters/s on {cpu['cores']} cores")
+
+    import torch
+    torch.cuda.set_device(0)
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     W = bulk_weights()
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     records, prof, levels = {}, None, 0
     for i, form in enumerate(forms):
-        rec, p, L = run_form(form, x_host, n, args, W, profile=(i == 0))
+        if i == 0:
+            warm, steps = args.warmup, args.steps
+        elif form in ("cold", "learned"):
+            warm, steps = 0, args.form_steps
+        else:
+            warm, steps = 1, args.form_steps
+        rec, p, L = run_form(form, x_host, n, args, W, profile=(i == 0), warmup=warm, steps=steps)
         records[form] = rec
         if i == 0:
             prof, levels = p, L
+    Cref = np.array(records[forms[0]]["C_first"])
+    for form, rec in records.items():
+        rec["C_first_rel_diff_vs_" + forms[0]] = float(
+            np.linalg.norm(np.array(rec["C_first"]) - Cref) / np.linalg.norm(Cref))
     head = records[forms[0]]
 
     # dominant level-0 kernel of the timed solves of the headline form
@@ -344,9 +394,10 @@ def main():
         "kernels": kernel_table,
         "forms": records,
     }
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(x_host, n, 32 if n >= 32 else n, 120)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    out["wall_s"] = time.perf_counter() - t_start
+    out["fits_in_driver_run"] = out["wall_s"] < 600.0
     print(json.dumps(out), flush=True)
 
 

@@ -65,7 +65,7 @@ typedef enum {
 typedef enum {
   HMG_FP64 = 0,        /* all fields, stencils and reductions in double        */
   HMG_FP32 = 1,        /* float fields/stencils, FP64 dots and coarsest solve  */
-  HMG_MIXED_BF16 = 2,  /* Sec. 5 mixed precision: the multigrid preconditioner
+  HMG_MIXED_BF16 = 2,  /* Sec. 4.1 / Sec. 6.3 (Tab. pre) mixed precision: the multigrid preconditioner
                           streams its vectors (smoother corrections, coarse
                           residuals and corrections) in bf16 and computes in
                           FP32; outer PCG vectors FP32, iterate FP64, FP64
@@ -74,7 +74,7 @@ typedef enum {
   HMG_MIXED_FP16 = 3,  /* reserved, not built: fp16 vectors cannot hold the
                           smoother corrections of soft regions (1/Emin scale)  */
   HMG_MIXED_BF16_STENCIL = 4 /* HMG_MIXED_BF16 with the coarse stencils and
-                          block inverses also in bf16 (Sec. 5: low-precision
+                          block inverses also in bf16 (Sec. 4.1: low-precision
                           stencils, higher-precision vectors).  The centre
                           block of a rounded stencil is never read: it is
                           minus the sum of the 26 stored blocks, applied in

@@ -1457,7 +1457,13 @@ hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double r
     for (size_t i = 0; i < w.size(); ++i) w[i] = (float)(wd[i] / sum);
     if (!ctx->fw) ctx->fw = (float*)ctx->arena.alloc(sizeof(float) * 7 * 7 * 7);
     if (!ctx->fw) return report(ctx, fail(HMG_E_OOM, "device allocation failed"));
-    (void)hipMemcpy(ctx->fw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice);
+    // earlier filter launches on the context stream may still read the old
+    // weights: the copy is ordered on that stream, and the host vector must
+    // outlive it
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return report(ctx, check_hip("filter"));
+    (void)hipMemcpyAsync(ctx->fw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice,
+                         ctx->stream);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return report(ctx, check_hip("filter"));
     ctx->fw_radius = radius;
   }
   density_filter(ctx->g0, in_dev, out_dev, ctx->fw, h, ctx->stream);

@@ -1,7 +1,11 @@
 """GPU checks of the batched solve (many cells in lockstep, one launch per
 level-0 pass, captured graphs): every cell must reproduce its standalone FP32
-solve (same algorithm; only the summation order of partial sums differs), and
-the autotuned launch shape must not change the results."""
+solve (same algorithm; only the summation order of partial sums differs), the
+cells of at most 24^3 vertices must match the FP64 oracle's C^H (stored in
+tests/golden/batch_small_cells.txt by a script that calls only the oracle) to
+1e-5, and the autotuned launch shape must not change the results."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -33,6 +37,19 @@ def densities():
     return out
 
 
+def golden_small_cells():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "batch_small_cells.txt")
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            out[parts[0]] = np.array([float(v) for v in parts[2:]])
+    return out
+
+
 def test_batch_matches_single_cell_solves():
     from paper_2301_08911_amd.hmg import Batch, Context
     rhos = densities()
@@ -43,6 +60,15 @@ def test_batch_matches_single_cell_solves():
     print("batch iters", res.iters.tolist(), flush=True)
     assert res.converged and (res.relres <= 1e-6).all()
     C = b.elastic_tensors()
+    G = golden_small_cells()
+    checked = 0
+    for k in range(len(SHAPES)):
+        if f"C{k}" in G:
+            e = rel(C[k], G[f"C{k}"].reshape(6, 6))
+            print("cell", k, SHAPES[k], "C^H vs oracle", e, flush=True)
+            assert e < 1e-5, (k, e)
+            checked += 1
+    assert checked == 4
     for k, (s, r) in enumerate(zip(SHAPES, rhos)):
         ctx = Context(s, precision="fp32")
         ctx.set_density(torch.from_numpy(r).cuda())
