@@ -59,6 +59,26 @@ MUTATIONS = {
     "prolongate odd weight": (
         "hmgref", "test_oracle", "odd = 0.5 * (U + np.roll(U, -1, axis=axis))",
         "odd = 0.5 * (U + np.roll(U, 1, axis=axis))"),
+    # design oracle
+    "symmetry mirror without the -1": (
+        "design", "test_oracle_design",
+        "img.append(dims[ax] - 1 - c if flips[ax] else c)",
+        "img.append(dims[ax] - c if flips[ax] else c)"),
+    "rotations taken as det -1": (
+        "design", "test_oracle_design",
+        'if kind == "rotate3" and det != 1:', 'if kind == "rotate3" and det != -1:'),
+    "sigmoid without the 1.5 V cap": (
+        "design", "test_oracle_design",
+        "vh = min(1.5 * volfrac, 1.0)", "vh = 1.0"),
+    "sensitivity filter without x weights": (
+        "design", "test_oracle_design",
+        "num += wt * np.roll(xv * gv,", "num += wt * np.roll(gv,"),
+    "log-Poisson gradient sign": (
+        "design", "test_oracle_design",
+        "dB = -eta * A / (B * (B + eta * A))", "dB = eta * A / (B * (B + eta * A))"),
+    "stop rule window of two": (
+        "design", "test_oracle_design",
+        "for k in range(len(f) - window, len(f)):", "for k in range(len(f) - window + 1, len(f)):"),
     # network oracle
     "conv tap x/z swapped": (
         "nnref", "test_nnref",
@@ -83,7 +103,7 @@ def _copy_tree(dst):
     shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(dst, "oracle"),
                     ignore=shutil.ignore_patterns("__pycache__"))
     shutil.copytree(os.path.join(ROOT, "tests", "golden"), os.path.join(dst, "tests", "golden"))
-    for f in ("conftest.py", "test_oracle.py", "test_nnref.py"):
+    for f in ("conftest.py", "test_oracle.py", "test_nnref.py", "test_oracle_design.py"):
         shutil.copy(os.path.join(ROOT, "tests", f), os.path.join(dst, "tests", f))
     os.makedirs(os.path.join(dst, "paper_2301_08911_amd"))
     for f in ("__init__.py", "inputs.py"):
@@ -110,7 +130,7 @@ def test_pins_catch_a_planted_mistake(name, tmp_path):
     assert "failed" in res.stdout
 
 
-@pytest.mark.parametrize("pins", ["test_oracle", "test_nnref"])
+@pytest.mark.parametrize("pins", ["test_oracle", "test_nnref", "test_oracle_design"])
 def test_unmutated_copy_passes(pins, tmp_path):
     """Control: the copied tree passes as is, so a failure above is the mistake's."""
     dst = str(tmp_path / "tree")
