@@ -165,12 +165,14 @@ def run_form(form, x0_host, n, args, W, profile, warmup, steps):
     import torch
     from paper_2301_08911_amd.hmg import Context
     shape = (n, n, n)
-    prec = form if form.startswith("mixed_bf16") else "fp32"
+    base = form[:-3] if form.endswith("_gs") else form
+    smoother = "gs" if form.endswith("_gs") else "jacobi"
+    prec = base if base.startswith("mixed_bf16") else "fp32"
     x = torch.from_numpy(x0_host.astype(np.float32).ravel()).cuda()
     rho, g, gx = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
-    ctx = Context(shape, precision=prec, Emin=1e-9)
+    ctx = Context(shape, precision=prec, Emin=1e-9, smoother=smoother)
     net = None
-    if form == "learned":
+    if base == "learned":
         from paper_2301_08911_amd import nn
         net = nn.Net()
         net.load(os.path.join(ROOT, "paper_2301_08911_amd", "weights", "warmstart_l4c8.npy"))
@@ -182,13 +184,13 @@ def run_form(form, x0_host, n, args, W, profile, warmup, steps):
         ctx.set_density(rho)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if form == "learned":
+        if base == "learned":
             from paper_2301_08911_amd import nn
             rr, used = nn.warm_start(ctx, net, 0.5)
             guesses.append((round(rr, 4), used))
             init = 1
         else:
-            init = 0 if (first or form == "cold") else 1
+            init = 0 if (first or base == "cold") else 1
         res = ctx.solve_cases(args.tol, args.max_iter, init=init)
         ts = time.perf_counter() - t0
         C = ctx.elastic_tensor()
@@ -221,11 +223,11 @@ def run_form(form, x0_host, n, args, W, profile, warmup, steps):
     rec = {"dof_iters_per_s": total_dofit / solve_s if solve_s > 0 else 0.0,
            "s_per_opt_iter": elapsed / steps, "solve_s_per_opt_iter": solve_s / steps,
            "pcg_iters": iters_all, "max_relres": relres_max, "bulk_modulus": Bs,
-           "precision": prec, "warmup": warmup, "steps": steps,
+           "precision": prec, "smoother": smoother, "warmup": warmup, "steps": steps,
            "start": {"plain": "previous iterate (zero on the first step)",
                      "mixed_bf16": "previous iterate (zero on the first step)",
                      "mixed_bf16_stencil": "previous iterate (zero on the first step)",
-                     "cold": "zero", "learned": "network guess, zero if rejected"}[form],
+                     "cold": "zero", "learned": "network guess, zero if rejected"}[base],
            "C_first": C_first[0].tolist()}
     if guesses:
         rec["warm_start_relres_used"] = guesses
@@ -296,8 +298,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
     ap.add_argument("--forms", default="plain,mixed_bf16,cold,learned",
-                    help="comma list of plain, mixed_bf16, mixed_bf16_stencil, learned, cold "
-                         "(the first is the headline and runs --warmup + --steps steps; the "
+                    help="comma list of plain, mixed_bf16, mixed_bf16_stencil, learned, cold, "
+                         "each optionally with the suffix _gs (eight-colour Gauss-Seidel smoother "
+                         "instead of damped Jacobi) (the first is the headline and runs --warmup + --steps steps; the "
                          "others run --form-steps timed steps after one warm-up step, none for "
                          "cold and learned, whose every step starts without the previous iterate)")
     ap.add_argument("--form-steps", type=int, default=1)
@@ -343,7 +346,7 @@ def main():
     for i, form in enumerate(forms):
         if i == 0:
             warm, steps = args.warmup, args.steps
-        elif form in ("cold", "learned"):
+        elif form.split("_gs")[0] in ("cold", "learned"):
             warm, steps = 0, args.form_steps
         else:
             warm, steps = 1, args.form_steps

@@ -13,8 +13,9 @@
  *                            level-2 stencil assembly, null-space removal);
  *   - filter and OC update:  Sec. 5.2 and Sec. 6 parameters.
  * The FE systems are solved by conjugate gradients preconditioned with one
- * geometric-multigrid V-cycle (damped 3x3 block-Jacobi smoothing, trilinear
- * prolongation, restriction = its transpose, FP64 direct coarsest solve).
+ * geometric-multigrid V-cycle (damped 3x3 block-Jacobi or eight-colour block
+ * Gauss-Seidel smoothing, trilinear prolongation, restriction = its
+ * transpose, FP64 direct coarsest solve).
  *
  * Conventions shared by every entry point
  *   - Index of vertex / element (x, y, z): idx = x + nx*(y + ny*z); the grid is
@@ -100,6 +101,21 @@ typedef struct hmg_config {
   int32_t precision;      /* hmg_precision                                     */
   int32_t replace_every;  /* recompute r = f - K x every k PCG iterations
                              (0 = never)                                      */
+  int32_t smoother;       /* 0 = damped 3x3 block Jacobi (omega above);
+                             1 = eight-colour symmetric block Gauss-Seidel
+                             (Sec. 4.1 vertex subsets, Sec. 4.2 Eq.
+                             (st-gs-relx)): colours (x mod 2) + 2 (y mod 2) +
+                             4 (z mod 2) relaxed 0..7 before the coarse
+                             correction and 7..0 after it; needs nx <= 1024;
+                             single cells only (the batch API rejects it)    */
+  int32_t post_fp16;      /* 1 = hmg_elastic_tensor and hmg_sensitivity read an
+                             FP16 cast of the displacements (Sec. 4.3, the
+                             cast before C^H and the sensitivity analysis),
+                             held in the residual buffer, and compute in FP32
+                             with FP64 sums; FP32-storage precisions only.
+                             C^H is second order in the rounding (the
+                             residual vanishes), the sensitivities first
+                             order (about 1e-3 relative)                      */
 } hmg_config;
 
 /* Create a context for one cell on the current HIP device.  `hip_stream` is a
@@ -169,6 +185,77 @@ hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double r
 
 /* Copy the last solution (field type, case-major SoA, zero mean) to u_dev. */
 hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev);
+
+/* ---- design-space steps of the optimization loop --------------------------- */
+
+/* Sensitivity filter (Sec. 5.3, the OC optimizer's filter of the sensitivity
+ * when the density itself is not filtered):
+ *   out_e = sum_f w_ef x_f g_f / (max(1e-3, x_e) sum_f w_ef),
+ * w the periodic cone weights of hmg_filter.  x_dev, g_dev, out_dev are
+ * float[n]; out must not overlap the inputs.  radius in (1, 4]. */
+hmg_status hmg_filter_sensitivity(hmg_ctx ctx, const float* x_dev, const float* g_dev,
+                                  float* out_dev, double radius);
+
+/* Symmetry groups of the cube (Sec. 6.1). */
+typedef enum {
+  HMG_SYM_REFLECT3 = 0, /* mirror planes x, y, z = 0.5 (8 elements); any box  */
+  HMG_SYM_REFLECT6 = 1, /* those and x = y, y = z, z = x (48); cubic cells    */
+  HMG_SYM_ROTATE3 = 2   /* quarter turns about the axes through the centre and
+                           their compositions (24); cubic cells                */
+} hmg_symmetry;
+
+/* Orbit averaging (Sec. 6.1): out_e = (1/|G|) sum_{g in G} in_{g(e)}, the
+ * element of cell coordinates c mapped by a signed axis permutation
+ * (c_a -> c_{perm a}, mirrored as N - 1 - c where flipped).  in_dev/out_dev
+ * are float[n] and must not overlap; the sum is taken in double.
+ * HMG_E_INVALID for an unknown kind or a non-cubic cell with reflect6 or
+ * rotate3. */
+hmg_status hmg_symmetrize(hmg_ctx ctx, const float* in_dev, float* out_dev, int32_t kind);
+
+/* Trigonometric initialization (Sec. 6.2).  With xb = R_q (x - (0.5, 0.5, 0.5)),
+ * x the element centre in [0, 1]^3 and R_q the rotation of the quaternion q
+ * (w, x, y, z; normalized here), T_n = cos(2 pi k xb_i), sin(2 pi k xb_i) in
+ * the order (axis i = 0..2, k = 1..nfreq, cos then sin) and Q_n = T_n
+ * followed by the products T_a T_b for a <= b (row-major in (a, b)):
+ *   y_e = sum_m weights[m] Q_m(x_e),
+ *   x_e = rho_min + Vh / (1 + exp(-k (y_e - mu))),  Vh = min(1.5 volfrac, 1),
+ * with mu by bisection (200 halvings of [min y - 40/k, max y + 40/k]) so that
+ * mean(x) = volfrac.  nfreq in 1..4; nweights must be 6 nfreq + 3 nfreq
+ * (6 nfreq + 1); weights and q are host arrays (the caller draws them);
+ * x_out_dev is float[n]; *mu_out (host, may be NULL) receives mu.  The paper
+ * uses k = 15 and rho_min = 1e-3.  Synchronizes. */
+hmg_status hmg_trig_init(hmg_ctx ctx, int32_t nfreq, const double q[4], const double* weights,
+                         int32_t nweights, double volfrac, double rho_min, double k_sigmoid,
+                         float* x_out_dev, double* mu_out);
+
+/* Objectives F(C^H) and W = dF/dC^H (Sec. 5.2 Eq. (bulk-obj), Sec. 5.3 Eq.
+ * (shear-obj), (poisson-relx), (poisson-new)); host only, no context or GPU.
+ * W is written entry by entry as the formula reads (row-major 6x6; C^H is
+ * symmetric, so the contraction with dC^H/drho is the same either way).
+ *   BULK            F = -(1/9) sum_{i,j<3} C_ij
+ *   SHEAR           F = -(C33 + C44 + C55) / 3
+ *   POISSON_RELAXED F = C01 + C02 + C12 - beta^iteration (C00 + C11 + C22)
+ *   POISSON_LOG     F = log(1 + eta A / B) + tau B^gamma,
+ *                   A = C01 + C12 + C20, B = C00 + C11 + C22
+ * params = {beta, eta, tau, gamma} or NULL for {0.8, 0.6, -1, 0.5} (the paper's
+ * eta, gamma and tau = -1/E0^gamma with E0 = 1; beta is the user's constant
+ * in (0, 1)); tau = NaN also selects -1.  HMG_E_INVALID for an unknown kind,
+ * beta outside (0, 1), or B <= 0 / 1 + eta A / B <= 0 for POISSON_LOG. */
+typedef enum {
+  HMG_OBJ_BULK = 0,
+  HMG_OBJ_SHEAR = 1,
+  HMG_OBJ_POISSON_RELAXED = 2,
+  HMG_OBJ_POISSON_LOG = 3
+} hmg_objective_kind;
+hmg_status hmg_objective(int32_t kind, const double C[36], int32_t iteration,
+                         const double* params, double* F_out, double W_out[36]);
+
+/* Stopping rule (Sec. 6): *stop_out = 1 once the relative change
+ * |F_k - F_{k-1}| / |F_{k-1}| of the objective history has stayed below
+ * rel_change for `window` consecutive iterations, or count >= max_iter; else 0.
+ * The paper's values are 5e-4, 3 and 300.  Host only. */
+hmg_status hmg_should_stop(const double* history, int32_t count, double rel_change,
+                           int32_t window, int32_t max_iter, int32_t* stop_out);
 
 /* Message of the last failed call on this context ("" if none). */
 const char* hmg_last_error(hmg_ctx ctx);

@@ -80,7 +80,9 @@ hmg_status hmg_nn_mse(hmg_nn net, const float* y_dev, const float* t_dev, int64_
  * by hmg_set_density onto the multigrid level whose size is the largest of
  * N, N/2, ... not above 64 (and divisible by 2^(levels-1)), predict u / N
  * there, multiply by N, remove the per-component mean, prolongate to the fine
- * grid with the solver's trilinear P, and apply one multigrid correction
+ * grid with the solver's trilinear P, scale each load case by its
+ * energy-optimal factor alpha = u.f / u.K u (the scaled guess is never further
+ * from the solution than zero in the energy norm), and apply one multigrid correction
  * u += M (f - K u) (a prediction that is right at low frequencies still
  * carries a large high-frequency residual on the fine grid, which one cycle
  * removes).  The result is kept as the iterate of the next

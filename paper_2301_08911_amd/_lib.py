@@ -11,7 +11,8 @@ SYMBOLS = (
     "hmg_sensitivity", "hmg_oc_update", "hmg_filter", "hmg_get_displacement", "hmg_last_error",
     "hmg_num_levels", "hmg_level_dims", "hmg_level_omega", "hmg_apply_operator", "hmg_get_stencil",
     "hmg_load_vectors", "hmg_vcycle", "hmg_transfer", "hmg_profile", "hmg_profile_read",
-    "hmg_element_constants",
+    "hmg_element_constants", "hmg_filter_sensitivity", "hmg_symmetrize", "hmg_trig_init",
+    "hmg_objective", "hmg_should_stop",
     "hmg_batch_create", "hmg_batch_destroy", "hmg_batch_set_density", "hmg_batch_tune",
     "hmg_batch_solve", "hmg_batch_elastic_tensors", "hmg_batch_last_error",
     # include/hmg_nn.h
@@ -30,7 +31,8 @@ class HmgConfig(ctypes.Structure):
         ("E0", ctypes.c_double), ("nu", ctypes.c_double), ("penal", ctypes.c_double),
         ("Emin", ctypes.c_double), ("levels", ctypes.c_int32), ("omega", ctypes.c_double),
         ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("replace_every", ctypes.c_int32),
+        ("replace_every", ctypes.c_int32), ("smoother", ctypes.c_int32),
+        ("post_fp16", ctypes.c_int32),
     ]
 
 
@@ -65,6 +67,11 @@ def load() -> ctypes.CDLL:
         "hmg_oc_update": ([vp, vp, vp, f64, f64, f64, f64, P(f64)], i32),
         "hmg_filter": ([vp, vp, vp, f64, i32], i32),
         "hmg_get_displacement": ([vp, vp], i32),
+        "hmg_filter_sensitivity": ([vp, vp, vp, vp, f64], i32),
+        "hmg_symmetrize": ([vp, vp, vp, i32], i32),
+        "hmg_trig_init": ([vp, i32, P(f64), P(f64), i32, f64, f64, f64, vp, P(f64)], i32),
+        "hmg_objective": ([i32, P(f64), i32, P(f64), P(f64), P(f64)], i32),
+        "hmg_should_stop": ([P(f64), i32, f64, i32, i32, P(i32)], i32),
         "hmg_last_error": ([vp], ctypes.c_char_p),
         "hmg_num_levels": ([vp, P(i32)], i32),
         "hmg_level_dims": ([vp, i32, P(i32)], i32),

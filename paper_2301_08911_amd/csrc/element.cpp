@@ -57,6 +57,33 @@ int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen
                                           mu * ((p == q ? tr : 0.0) + grad_integral(a, q, b, p));
         }
 
+  // ---- the ten distinct magnitudes of K0 (k0_sel), checked against K0
+  {
+    const double M[2] = {1.0 / 6.0, 1.0 / 3.0}, G[2] = {-1.0, 1.0};
+    for (int ei = 0; ei < 2; ++ei)
+      for (int c = 0; c < 3; ++c) {
+        const int ej = c >= 1 ? 1 : 0, em = c >= 2 ? 1 : 0;
+        out->kv[3 * ei + c] = (lam + 2 * mu) * G[ei] * M[ej] * M[em] +
+                              mu * M[ei] * (G[ej] * M[em] + G[em] * M[ej]);
+      }
+    for (int em = 0; em < 2; ++em) {
+      out->kv[6 + 2 * em] = (lam - mu) * M[em] / 4.0;
+      out->kv[6 + 2 * em + 1] = (lam + mu) * M[em] / 4.0;
+    }
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b)
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q) {
+            const int sel = k0_sel(a, p, b, q);
+            const double v = (sel & 1) ? -out->kv[sel >> 1] : out->kv[sel >> 1];
+            if (std::fabs(v - out->K0[3 * a + p][3 * b + q]) > 1e-14) {
+              std::snprintf(err, errlen, "K0 entry (%d,%d) does not follow its selector",
+                            3 * a + p, 3 * b + q);
+              return 1;
+            }
+          }
+  }
+
   // ---- mode form Kt = H K0 H / 64
   double Kt[24][24];
   auto H = [](int a, int m) { return (__builtin_popcount(a & m) & 1) ? -1.0 : 1.0; };

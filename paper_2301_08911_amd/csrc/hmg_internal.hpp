@@ -55,6 +55,32 @@ struct LoadTpl {
   T g[NCASE][8][3];
 };
 
+// Every entry of K0 (unit brick, E = 1, isotropic) is plus or minus one of ten
+// values, selected by the bits of the two nodes and the two components:
+//   same component i:  v[3 e_i + c], e_i = [a_i == b_i], c = number of the
+//                      other two axes on which a and b agree;
+//   components i != j: (lambda +- mu) M_m / 4 with m the third axis,
+//                      M_m = 1/3 if a_m == b_m else 1/6: v[6 + 2 e_m + g],
+//                      g = 1 for lambda + mu (the two sign products agree),
+//                      sign s(a_i) s(b_j) with s(0) = -1, s(1) = +1.
+// k0_sel returns (index << 1) | negative.  build_element_consts checks that the
+// ten values rebuild K0 exactly.
+__host__ __device__ constexpr int k0_sel(int a, int i, int b, int j) {
+  if (i == j) {
+    int c = 0;
+    for (int k = 0; k < 3; ++k)
+      if (k != i && ((a >> k) & 1) == ((b >> k) & 1)) ++c;
+    const int ei = ((a >> i) & 1) == ((b >> i) & 1) ? 1 : 0;
+    return (3 * ei + c) << 1;
+  }
+  const int m = 3 - i - j;
+  const int em = ((a >> m) & 1) == ((b >> m) & 1) ? 1 : 0;
+  const int sai = ((a >> i) & 1) ? 1 : -1, sbj = ((b >> j) & 1) ? 1 : -1;
+  const int saj = ((a >> j) & 1) ? 1 : -1, sbi = ((b >> i) & 1) ? 1 : -1;
+  const int g = sai * sbj == saj * sbi ? 1 : 0;
+  return ((6 + 2 * em + g) << 1) | (sai * sbj < 0 ? 1 : 0);
+}
+
 // Everything the library derives from (E = 1, nu) on the host, in double.
 struct ElementConsts {
   double K0[24][24];          // element stiffness, dof 3a+k
@@ -65,6 +91,7 @@ struct ElementConsts {
   double msig[8][24][24];     // W_sigma^T K0 W_sigma for the 8 sub-element positions
   double lam0;                // max eigenvalue of blockdiag(K0)^-1 K0: bounds the level-0
                               // block-Jacobi spectrum for any densities
+  double kv[10];              // the ten distinct magnitudes of K0 (k0_sel)
 };
 
 // Returns 0 on success; fills `err` otherwise.
@@ -277,14 +304,63 @@ template <typename R, typename T>
 void coarse_solve(const Grid& g, const double* Ainv, const R* r, T* z, const double* scal,
                   hipStream_t stm);
 
+// ---------------------------------------------------------------- Gauss-Seidel
+// Eight-colour symmetric block Gauss-Seidel sweeps (gs.hip).  A forward sweep
+// relaxes colours 0..7, a backward sweep 7..0; "fresh" marks a forward sweep
+// whose z starts at zero (z need not be cleared).  The right-hand side is
+// r - m with m from the S_MEAN* slots of `mean` (NULL: no shift).
+// True if the grid's rows fit the level-0 kernels (even extents, nx <= 1024).
+bool gs_supported(const Grid& g);
+// Level 0, matrix free (k0v: the ten magnitudes of K0, ElementConsts::kv, on
+// the host).  With nblk_out set (backward sweeps), partials of (r - m).z go to
+// slot S_RZNEW and, if q is given, of q.z to S_QZ; *nblk_out receives their
+// count.
+template <typename T>
+void gs0_sweep(const Grid& g, const double* k0v, const T* s, const T* r, const double* mean, T* z,
+               const T* q, const double* scal, Partials part, bool forward, bool fresh,
+               int* nblk_out, hipStream_t st);
+int gs0_blocks_per_case(const Grid& g);
+// Coarse levels from stored stencils; dinv holds the undamped block inverses.
+template <typename V, typename W>
+void gsc_sweep(const Grid& g, const W* st, const W* dinv, const V* r, const double* mean, V* z,
+               const double* scal, bool forward, bool fresh, hipStream_t stm);
+
+// ---------------------------------------------------------------- design space
+// Symmetry group as signed axis permutations (design.hip): code[t] =
+// perm0 | perm1 << 2 | perm2 << 4 | flips << 6; output axis a takes input
+// axis perm_a, mirrored (c -> N - 1 - c) when bit a of flips is set.
+struct SymOps {
+  int count = 0;
+  int code[48] = {};
+};
+void symmetrize(const Grid& g, const float* in, float* out, const SymOps& ops, hipStream_t st);
+constexpr int TRIG_MAX_FREQ = 4;
+constexpr int TRIG_MAX_WEIGHTS = 6 * TRIG_MAX_FREQ + 3 * TRIG_MAX_FREQ * (6 * TRIG_MAX_FREQ + 1);
+struct TrigBasis {
+  double R[9];  // rotation of the centred element coordinates
+  int nfreq;    // 1..TRIG_MAX_FREQ
+};
+// y = sum_m w_m Q_m(x_e) (w: 6 nfreq + 6 nfreq (6 nfreq + 1) / 2 doubles on the device)
+void trig_field(const Grid& g, const TrigBasis& tb, const double* w_dev, float* y,
+                hipStream_t st);
+// y <- rho_min + Vh / (1 + exp(-k (y - mu))) with mu by `steps` bisection steps
+// on the mean; state (4 doubles) ends with mu in state[3].  part needs a stride
+// of at least 4096 and two rows.
+void sigmoid_project(const Grid& g, float* y, double volfrac, double rho_min, double k,
+                     double* state, Partials part, int steps, hipStream_t st);
+// out = H(x g) / max(1e-3, x) with the normalized cone weights w_dev
+void sensitivity_filter(const Grid& g, const float* x, const float* gin, float* out,
+                        const float* w_dev, int h, hipStream_t st);
+
 // ---------------------------------------------------------------- post-processing
-template <typename T>
+// u is stored as U: the arithmetic type, or FP16 (the cast of Sec. 4.3, with T = float)
+template <typename T, typename U>
 void elastic_partials(const Grid& g, const ModeK<T>& mk, const LoadTpl<T>& chihat, const T* s,
-                      const T* u, Partials part, int* nblk_out, hipStream_t st);
+                      const U* u, Partials part, int* nblk_out, hipStream_t st);
 void elastic_finalize(const Partials& part, int nblk, int64_t n, double* out36, hipStream_t st);
-template <typename T>
+template <typename T, typename U>
 void sensitivity(const Grid& g, const ModeK<T>& mk, const LoadTpl<T>& chihat, const T* rho,
-                 const T* u, const double* w21_dev, double coef, double penal, float* out,
+                 const U* u, const double* w21_dev, double coef, double penal, float* out,
                  hipStream_t st);
 void density_filter(const Grid& g, const float* in, float* out, const float* w_dev, int h,
                     hipStream_t st);

@@ -73,9 +73,10 @@ __device__ __forceinline__ void kt_apply(const ModeK<T>& K, const T (&d)[8][3], 
   o[0][0] = o[0][1] = o[0][2] = T(0);
 }
 
-// d_hat^c for the six cases of element i (modes 0..7; mode 0 unused).
-template <typename T>
-__device__ __forceinline__ void element_dhat(const Grid& g, int64_t i, const T* __restrict__ u,
+// d_hat^c for the six cases of element i (modes 0..7; mode 0 unused); u is
+// stored as U (the arithmetic type T, or FP16 for the cast of Sec. 4.3).
+template <typename T, typename U>
+__device__ __forceinline__ void element_dhat(const Grid& g, int64_t i, const U* __restrict__ u,
                                              const LoadTpl<T>& chh, T (&dh)[NCASE][8][3]) {
   const int gx = (int)(i % g.nx);
   const int gy = (int)((i / g.nx) % g.ny);
@@ -93,7 +94,7 @@ __device__ __forceinline__ void element_dhat(const Grid& g, int64_t i, const T* 
     for (int k = 0; k < 3; ++k) {
       T v[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) v[a] = u[(int64_t)(c * 3 + k) * g.n + node[a]];
+      for (int a = 0; a < 8; ++a) v[a] = (T)u[(int64_t)(c * 3 + k) * g.n + node[a]];
       // 8-point Walsh-Hadamard transform, bit 0 then 1 then 2
 #pragma unroll
       for (int h = 1; h < 8; h <<= 1)
@@ -119,10 +120,10 @@ __device__ __forceinline__ T mode_dot(const T (&a)[8][3], const T (&b)[8][3]) {
   return s;
 }
 
-template <typename T>
+template <typename T, typename U>
 __global__ void __launch_bounds__(PB) elastic_kernel(Grid g, ModeK<T> mk, LoadTpl<T> chh,
                                                      const T* __restrict__ s,
-                                                     const T* __restrict__ u, Partials part) {
+                                                     const U* __restrict__ u, Partials part) {
   __shared__ double red[PB / 64];
   double acc[21];
 #pragma unroll
@@ -165,10 +166,10 @@ __global__ void __launch_bounds__(256) elastic_fin_kernel(Partials part, int nbl
   }
 }
 
-template <typename T>
+template <typename T, typename U>
 __global__ void __launch_bounds__(PB) sens_kernel(Grid g, ModeK<T> mk, LoadTpl<T> chh,
                                                   const T* __restrict__ rho,
-                                                  const T* __restrict__ u,
+                                                  const U* __restrict__ u,
                                                   const double* __restrict__ w21, double coef,
                                                   double penal, float* __restrict__ out) {
   double w[21];
@@ -294,21 +295,21 @@ __global__ void __launch_bounds__(PB) oc_apply_kernel(Grid g, float* __restrict_
 
 }  // namespace
 
-template <typename T>
+template <typename T, typename U>
 void elastic_partials(const Grid& g, const ModeK<T>& mk, const LoadTpl<T>& chihat, const T* s,
-                      const T* u, Partials part, int* nblk_out, hipStream_t st) {
+                      const U* u, Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  hipLaunchKernelGGL(elastic_kernel<T>, dim3(nb), dim3(PB), 0, st, g, mk, chihat, s, u, part);
+  hipLaunchKernelGGL((elastic_kernel<T, U>), dim3(nb), dim3(PB), 0, st, g, mk, chihat, s, u, part);
   *nblk_out = nb;
 }
 void elastic_finalize(const Partials& part, int nblk, int64_t n, double* out36, hipStream_t st) {
   hipLaunchKernelGGL(elastic_fin_kernel, dim3(21), dim3(256), 0, st, part, nblk, n, out36);
 }
-template <typename T>
+template <typename T, typename U>
 void sensitivity(const Grid& g, const ModeK<T>& mk, const LoadTpl<T>& chihat, const T* rho,
-                 const T* u, const double* w21_dev, double coef, double penal, float* out,
+                 const U* u, const double* w21_dev, double coef, double penal, float* out,
                  hipStream_t st) {
-  hipLaunchKernelGGL(sens_kernel<T>, dim3(blocks_for(g.n)), dim3(PB), 0, st, g, mk, chihat, rho, u,
+  hipLaunchKernelGGL((sens_kernel<T, U>), dim3(blocks_for(g.n)), dim3(PB), 0, st, g, mk, chihat, rho, u,
                      w21_dev, coef, penal, out);
 }
 void density_filter(const Grid& g, const float* in, float* out, const float* w_dev, int h,
@@ -335,13 +336,14 @@ void oc_init(double* state, hipStream_t st) {
   hipLaunchKernelGGL(oc_init_kernel, dim3(1), dim3(64), 0, st, state);
 }
 
-#define HMG_INST(T)                                                                            \
-  template void elastic_partials<T>(const Grid&, const ModeK<T>&, const LoadTpl<T>&, const T*, \
-                                    const T*, Partials, int*, hipStream_t);                    \
-  template void sensitivity<T>(const Grid&, const ModeK<T>&, const LoadTpl<T>&, const T*,      \
-                               const T*, const double*, double, double, float*, hipStream_t);
-HMG_INST(float)
-HMG_INST(double)
+#define HMG_INST(T, U)                                                                          \
+  template void elastic_partials<T, U>(const Grid&, const ModeK<T>&, const LoadTpl<T>&, const T*, \
+                                       const U*, Partials, int*, hipStream_t);                    \
+  template void sensitivity<T, U>(const Grid&, const ModeK<T>&, const LoadTpl<T>&, const T*,      \
+                                  const U*, const double*, double, double, float*, hipStream_t);
+HMG_INST(float, float)
+HMG_INST(double, double)
+HMG_INST(float, f16)
 #undef HMG_INST
 
 }  // namespace hmg

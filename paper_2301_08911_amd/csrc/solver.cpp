@@ -216,6 +216,7 @@ class Solver final : public SolverIface {
           tpl_.g[c][a][k] = (T)ec_.load[c][a][k];
           tpl64_.g[c][a][k] = ec_.load[c][a][k];
           chh64_.g[c][a][k] = ec_.chihat[c][a][k];
+          chh32_.g[c][a][k] = (float)ec_.chihat[c][a][k];
         }
     auto A = [&](size_t bytes) { return arena_.alloc(bytes); };
     s_ = (T*)A(sizeof(T) * g0.n);
@@ -258,6 +259,7 @@ class Solver final : public SolverIface {
     Ainv_ = (double*)A(sizeof(double) * ((size_t)ncdof_ * ncdof_ + ncdof_));
     if (L == 1) st0_ = (T*)A(sizeof(T) * 243 * g0.n);
     stride_ = std::max(op0_blocks_per_case(g0), 4096);
+    if (gs_) stride_ = std::max(stride_, 4 * gs0_blocks_per_case(g0));
     part_.buf = (double*)A(sizeof(double) * (size_t)S_NSLOT * 8 * stride_);
     part_.stride = stride_;
     scal_ = (double*)A(sizeof(double) * S_NSLOT * 8);
@@ -282,6 +284,7 @@ class Solver final : public SolverIface {
     (void)hipMemcpyAsync(K0dev_, &ec_.K0[0][0], sizeof(double) * 576, hipMemcpyHostToDevice, st_);
     (void)hipMemcpyAsync(msig_, &ec_.msig[0][0][0], sizeof(double) * 8 * 576, hipMemcpyHostToDevice,
                    st_);
+
     vec_fill<double>(x_, F, 0.0, st_);
     HMG_TRY(check_hip("init"));
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("init sync");
@@ -297,6 +300,7 @@ class Solver final : public SolverIface {
   // network prediction of u/N there, times N, zero mean per component,
   // trilinear prolongation to the fine grid, FP64 residual test.
   Status warm_start(Net& net, double accept, double* relres, int* used) override {
+    fp16_ready_ = false;
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
     const Grid& g0 = grids_[0];
     if (g0.nx != g0.ny || g0.nx != g0.nz) return fail(HMG_E_INVALID, "warm start needs a cubic cell");
@@ -356,6 +360,28 @@ class Solver final : public SolverIface {
       *out = w;
       return Status{};
     };
+    // Energy-optimal scale of every case's guess: alpha = u.f / u.K u minimizes
+    // the energy error ||u* - alpha u||_K over alpha, so the scaled guess is
+    // never further from the solution in that norm than the zero start.
+    {
+      T* fbuf = q_;  // free until the solve
+      int nbd = 0;
+      scal_set_all_active(aux_, st_);
+      forcing<T>(g0, tpl64_, s64_, fbuf, part_, &nbd, st_);
+      vec_dot_cases<double, T>(g0, x_, fbuf, aux_, part_, S_PQ, &nbd, st_);
+      fin_sum(part_, S_PQ, nbd, aux_, true, st_);  // u.f
+      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nbd);
+      vec_dot_cases<double, T>(g0, x_, r_, aux_, part_, S_RZ, &nbd, st_);
+      fin_sum(part_, S_RZ, nbd, aux_, true, st_);  // u.(f - K u)
+      HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
+      const double* ha = hscal_ + S_NSLOT * 8;
+      const int64_t cs = 3 * g0.n;
+      for (int c = 0; c < NCASE; ++c) {
+        const double uf = ha[S_PQ * 8 + c], uku = uf - ha[S_RZ * 8 + c];
+        guess_scale_[c] = uku > 0.0 ? uf / uku : 0.0;
+        vec_scale<double>(x_ + c * cs, cs, guess_scale_[c], st_);
+      }
+    }
     double raw = 0.0, worst = 0.0;
     HMG_TRY(worst_relres(&raw));
     vec_mean_partial<T>(g0, r_, part_, &nb, st_);
@@ -391,8 +417,10 @@ class Solver final : public SolverIface {
     omega_.assign(L, 0.0);
     lambda_.assign(L, 0.0);
     lambda_[0] = ec_.lam0;
-    omega_[0] = omega_for(ec_.lam0);
-    dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
+    // Gauss-Seidel needs no damping: level 0 forms its blocks from s on the
+    // fly, coarse levels keep the undamped inverses.
+    omega_[0] = gs_ ? 1.0 : omega_for(ec_.lam0);
+    if (!gs_) dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
     for (int l = 1; l < L; ++l) {
       if (l == 1)
         galerkin_first<T, W>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
@@ -400,6 +428,10 @@ class Solver final : public SolverIface {
         galerkin_next<W>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
       if (l == L - 1) continue;  // the coarsest level is solved directly
       dinv_from_stencil<W>(grids_[l], lev_[l].st, 1.0, lev_[l].dinv, st_);
+      if (gs_) {
+        omega_[l] = 1.0;
+        continue;
+      }
       double lam = 0.0;
       HMG_TRY(estimate_lambda(l, &lam));
       lambda_[l] = lam;
@@ -425,6 +457,7 @@ class Solver final : public SolverIface {
 
   Status solve(double tol, int max_iter, int init, const void* u0, int iters[6],
                double relres[6]) override {
+    fp16_ready_ = false;
     if (!have_density_) return fail(HMG_E_STATE, "hmg_set_density has not been called");
     if (!(tol > 0.0) || max_iter <= 0 || init < 0 || init > 2 || (init == 2 && !u0))
       return fail(HMG_E_INVALID, "bad solve arguments (tol %g, max_iter %d, init %d)", tol,
@@ -578,15 +611,32 @@ class Solver final : public SolverIface {
     }
     have_solution_ = true;
     have_iterate_ = true;
+    fp16_ready_ = false;
     if (any(active))
       return fail(HMG_E_NOT_CONVERGED, "max_iter %d reached before rel_tol %g", max_iter, tol);
     return Status{};
   }
 
+  // FP16 copy of the solution for C^H and the sensitivities (Sec. 4.3), kept in
+  // the residual buffer, which the solve no longer needs; FP32-storage forms only.
+  const f16* fp16_solution() {
+    if (!fp16_ready_) {
+      vec_convert<double, f16>(reinterpret_cast<f16*>(r_), x_, (int64_t)NCASE * 3 * grids_[0].n,
+                               st_);
+      fp16_ready_ = true;
+    }
+    return reinterpret_cast<const f16*>(r_);
+  }
+  bool use_fp16() const { return cfg_.post_fp16 != 0 && sizeof(T) == sizeof(float); }
+
   Status elastic(double C[36]) override {
     if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
     int nb = 0;
-    elastic_partials<double>(grids_[0], mk64_, chh64_, s64_, x_, part_, &nb, st_);
+    if (use_fp16())
+      elastic_partials<float, f16>(grids_[0], cast_mode_f(mk64_), chh32_, (const float*)s_,
+                                   fp16_solution(), part_, &nb, st_);
+    else
+      elastic_partials<double, double>(grids_[0], mk64_, chh64_, s64_, x_, part_, &nb, st_);
     elastic_finalize(part_, nb, grids_[0].n, misc_, st_);
     (void)hipMemcpyAsync(C, misc_, sizeof(double) * 36, hipMemcpyDeviceToHost, st_);
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("elastic_tensor");
@@ -602,8 +652,12 @@ class Solver final : public SolverIface {
         w21[t++] = (i == j) ? Wt[i * 6 + i] : Wt[i * 6 + j] + Wt[j * 6 + i];
     (void)hipMemcpyAsync(misc_ + 36, w21, sizeof(double) * 21, hipMemcpyHostToDevice, st_);
     const double coef = cfg_.penal * (cfg_.E0 - cfg_.Emin) / (double)grids_[0].n;
-    sensitivity<double>(grids_[0], mk64_, chh64_, rho64_, x_, misc_ + 36, coef, cfg_.penal, out,
-                        st_);
+    if (use_fp16())
+      sensitivity<float, f16>(grids_[0], cast_mode_f(mk64_), chh32_, (const float*)rho_,
+                              fp16_solution(), misc_ + 36, coef, cfg_.penal, out, st_);
+    else
+      sensitivity<double, double>(grids_[0], mk64_, chh64_, rho64_, x_, misc_ + 36, coef,
+                                  cfg_.penal, out, st_);
     // the host array w21 must outlive the copy
     if (hipStreamSynchronize(st_) != hipSuccess) return check_hip("sensitivity");
     return check_hip("sensitivity");
@@ -687,6 +741,10 @@ class Solver final : public SolverIface {
 
   static ModeK<T> cast_mode(const ModeK<double>& m) {
     return ModeK<T>{(T)m.ab, (T)m.b, (T)m.cs, (T)m.p, (T)m.q, (T)m.fg, (T)m.g, (T)m.z};
+  }
+  static ModeK<float> cast_mode_f(const ModeK<double>& m) {
+    return ModeK<float>{(float)m.ab, (float)m.b, (float)m.cs, (float)m.p,
+                        (float)m.q,  (float)m.fg, (float)m.g, (float)m.z};
   }
   // Damping of block Jacobi on a level whose spectrum bound is lam: 1.6/lam
   // (near the smoothing optimum 2/(lam + lam/4)); a configured omega is used
@@ -773,6 +831,20 @@ class Solver final : public SolverIface {
     }
     Op0Launch<T> L0{g0, mk_, s_, st_};
     const double vn = (double)g0.n, TB = sizeof(T), VB = sizeof(V), nact = active_count_;
+    if (gs_) {
+      // forward sweep from zero, residual + restriction, coarse correction,
+      // backward sweep with the partial dot products of the result
+      gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, nullptr, scal, part_, true, true, nullptr, st_);
+      op0_residual<T, V>(L0, r0, zout, t_, scal);
+      restrict_to<V>(g0, grids_[1], t_, lev_[1].r, scal, st_);
+      descend(1, scal);
+      if (L == 2)
+        prolong_add<T, T>(g0, grids_[1], zout, zc_, scal, false, st_);
+      else
+        prolong_add<T, V>(g0, grids_[1], zout, lev_[1].z, scal, false, st_);
+      gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, qpr, scal, part_, false, false, nb, st_);
+      return check_hip("vcycle");
+    }
     clock.timed(HMG_K_JACOBI, vn * (nact * 6 * TB + 6 * TB), st_,
                 [&] { vec_jacobi0<T, T, T>(g0, r0, dinv0_, w0_, scal, scal, st_); });
     clock.timed(HMG_K_RESIDUAL, vn * (nact * 3 * (2 * TB + VB) + TB), st_,
@@ -800,6 +872,18 @@ class Solver final : public SolverIface {
     int nb = 0;
     vec_mean_partial<V>(g, lv.r, part_, &nb, st_);
     fin_mean(part_, nb, g.n, lv.ms, st_);
+    if (gs_) {
+      gsc_sweep<V, W>(g, lv.st, lv.dinv, lv.r, lv.ms, lv.z, scal, true, true, st_);
+      kc_residual<V, W>(g, lv.st, lv.z, lv.r, lv.t, scal, lv.ms, st_);
+      restrict_to<V>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
+      descend(l + 1, scal);
+      if (l + 1 == L - 1)
+        prolong_add<V, T>(g, grids_[l + 1], lv.z, zc_, scal, false, st_);
+      else
+        prolong_add<V, V>(g, grids_[l + 1], lv.z, lev_[l + 1].z, scal, false, st_);
+      gsc_sweep<V, W>(g, lv.st, lv.dinv, lv.r, lv.ms, lv.z, scal, false, false, st_);
+      return;
+    }
     vec_jacobi0<V, W, V>(g, lv.r, lv.dinv, lv.z, scal, lv.ms, st_);
     kc_residual<V, W>(g, lv.st, lv.z, lv.r, lv.t, scal, lv.ms, st_);
     restrict_to<V>(g, grids_[l + 1], lv.t, lev_[l + 1].r, scal, st_);
@@ -822,6 +906,8 @@ class Solver final : public SolverIface {
   LoadTpl<T> tpl_{};
   LoadTpl<double> tpl64_{};
   LoadTpl<double> chh64_{};
+  LoadTpl<float> chh32_{};
+  bool fp16_ready_ = false;  // r_ holds the FP16 cast of the current solution
   T *s_ = nullptr, *rho_ = nullptr, *dinv0_ = nullptr;
   double* s64_ = nullptr;    // FP64 copies used by the residual recomputation and C^H
   double* rho64_ = nullptr;
@@ -841,6 +927,7 @@ class Solver final : public SolverIface {
   int stride_ = 0;
   double *scal_ = nullptr, *aux_ = nullptr, *misc_ = nullptr;
   double *K0dev_ = nullptr, *msig_ = nullptr;
+  bool gs_ = cfg_.smoother == 1;  // eight-colour symmetric Gauss-Seidel instead of damped Jacobi
   int* bad_ = nullptr;
   double* hscal_ = nullptr;  // pinned: device scalars read back (main, aux)
   double* hstage_ = nullptr; // pinned: staging for host-to-device masks
@@ -854,6 +941,7 @@ class Solver final : public SolverIface {
   bool have_iterate_ = false;   // x_ holds a solution or an accepted guess (init = 1)
   float* nnbuf_ = nullptr;      // warm start: network input and output (<= 64^3)
   double raw_relres_ = 0.0;     // warm start: relative residual before the correction cycle
+  double guess_scale_[NCASE] = {};  // warm start: energy-optimal scale of each case's guess
 };
 
 
@@ -1274,6 +1362,7 @@ struct hmg_ctx_s {
   Partials ocpart{};
   float* fw = nullptr;      // filter weights, (2h+1)^3
   double fw_radius = -1.0;
+  double* tw = nullptr;     // trigonometric-initialization weights
 };
 
 namespace {
@@ -1301,6 +1390,13 @@ Status validate(const hmg_config& c, std::vector<Grid>* grids) {
       c.precision != HMG_MIXED_BF16_STENCIL)
     return fail(HMG_E_INVALID, "precision %d is not built in this library", c.precision);
   if (c.levels < 0 || c.replace_every < 0) return fail(HMG_E_INVALID, "bad levels/replace_every");
+  if (c.smoother != 0 && c.smoother != 1)
+    return fail(HMG_E_INVALID, "smoother must be 0 (damped block Jacobi) or 1 (Gauss-Seidel)");
+  if (c.post_fp16 != 0 && c.post_fp16 != 1) return fail(HMG_E_INVALID, "post_fp16 must be 0 or 1");
+  if (c.post_fp16 == 1 && c.precision == HMG_FP64)
+    return fail(HMG_E_INVALID, "the FP16 displacement cast needs an FP32-storage precision");
+  if (c.smoother == 1 && c.nx > 1024)
+    return fail(HMG_E_INVALID, "the Gauss-Seidel smoother takes at most 1024 cells along x");
   grids->clear();
   Grid g{c.nx, c.ny, c.nz, (int64_t)c.nx * c.ny * c.nz};
   grids->push_back(g);
@@ -1357,9 +1453,11 @@ hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out) {
   s = ctx->solver->init();
   if (s.code == HMG_OK) {
     ctx->ocstate = (double*)ctx->arena.alloc(sizeof(double) * 8);
-    ctx->ocpart.buf = (double*)ctx->arena.alloc(sizeof(double) * 4096);
+    ctx->ocpart.buf = (double*)ctx->arena.alloc(sizeof(double) * 2 * 4096);
     ctx->ocpart.stride = 4096;
-    if (!ctx->ocstate || !ctx->ocpart.buf) s = fail(HMG_E_OOM, "device allocation failed");
+    ctx->tw = (double*)ctx->arena.alloc(sizeof(double) * TRIG_MAX_WEIGHTS);
+    if (!ctx->ocstate || !ctx->ocpart.buf || !ctx->tw)
+      s = fail(HMG_E_OOM, "device allocation failed");
   }
   if (s.code != HMG_OK) {
     std::fprintf(stderr, "hmg_create: %s\n", s.msg.c_str());
@@ -1432,14 +1530,11 @@ hmg_status hmg_oc_update(hmg_ctx ctx, float* x_dev, const float* dfdx_dev, doubl
   return report(ctx, check_hip("oc_update"));
 }
 
-hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double radius,
-                      int32_t adjoint) {
-  (void)adjoint;  // the cone filter is symmetric: H^T = H
-  if (!ctx) return HMG_E_INVALID;
-  if (!in_dev || !out_dev || in_dev == out_dev)
-    return report(ctx, fail(HMG_E_INVALID, "filter needs distinct non-NULL buffers"));
-  if (!(radius > 1.0 && radius <= 4.0))
-    return report(ctx, fail(HMG_E_INVALID, "radius must be in (1, 4]"));
+}  // extern "C"
+
+namespace {
+// Normalized cone weights of `radius` in ctx->fw (uploaded when the radius changes).
+Status filter_weights(hmg_ctx ctx, double radius) {
   const int h = (int)std::ceil(radius) - 1;
   if (radius != ctx->fw_radius) {
     const int span = 2 * h + 1;
@@ -1456,18 +1551,175 @@ hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double r
         }
     for (size_t i = 0; i < w.size(); ++i) w[i] = (float)(wd[i] / sum);
     if (!ctx->fw) ctx->fw = (float*)ctx->arena.alloc(sizeof(float) * 7 * 7 * 7);
-    if (!ctx->fw) return report(ctx, fail(HMG_E_OOM, "device allocation failed"));
+    if (!ctx->fw) return fail(HMG_E_OOM, "device allocation failed");
     // earlier filter launches on the context stream may still read the old
     // weights: the copy is ordered on that stream, and the host vector must
     // outlive it
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return report(ctx, check_hip("filter"));
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return check_hip("filter");
     (void)hipMemcpyAsync(ctx->fw, w.data(), sizeof(float) * w.size(), hipMemcpyHostToDevice,
                          ctx->stream);
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return report(ctx, check_hip("filter"));
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return check_hip("filter");
     ctx->fw_radius = radius;
   }
-  density_filter(ctx->g0, in_dev, out_dev, ctx->fw, h, ctx->stream);
+  return Status{};
+}
+}  // namespace
+
+extern "C" {
+
+hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double radius,
+                      int32_t adjoint) {
+  (void)adjoint;  // the cone filter is symmetric: H^T = H
+  if (!ctx) return HMG_E_INVALID;
+  if (!in_dev || !out_dev || in_dev == out_dev)
+    return report(ctx, fail(HMG_E_INVALID, "filter needs distinct non-NULL buffers"));
+  if (!(radius > 1.0 && radius <= 4.0))
+    return report(ctx, fail(HMG_E_INVALID, "radius must be in (1, 4]"));
+  Status st = filter_weights(ctx, radius);
+  if (st.code != HMG_OK) return report(ctx, st);
+  density_filter(ctx->g0, in_dev, out_dev, ctx->fw, (int)std::ceil(radius) - 1, ctx->stream);
   return report(ctx, check_hip("filter"));
+}
+
+hmg_status hmg_filter_sensitivity(hmg_ctx ctx, const float* x_dev, const float* g_dev,
+                                  float* out_dev, double radius) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!x_dev || !g_dev || !out_dev || out_dev == x_dev || out_dev == g_dev)
+    return report(ctx, fail(HMG_E_INVALID, "sensitivity filter needs distinct non-NULL buffers"));
+  if (!(radius > 1.0 && radius <= 4.0))
+    return report(ctx, fail(HMG_E_INVALID, "radius must be in (1, 4]"));
+  Status st = filter_weights(ctx, radius);
+  if (st.code != HMG_OK) return report(ctx, st);
+  sensitivity_filter(ctx->g0, x_dev, g_dev, out_dev, ctx->fw, (int)std::ceil(radius) - 1,
+                     ctx->stream);
+  return report(ctx, check_hip("filter_sensitivity"));
+}
+
+hmg_status hmg_objective(int32_t kind, const double C[36], int32_t iteration,
+                         const double* params, double* F_out, double W_out[36]) {
+  if (!C || !F_out || !W_out || iteration < 0) return HMG_E_INVALID;
+  // beta, eta, tau, gamma (tau = NaN: -1 / E0^gamma with E0 = 1)
+  double beta = 0.8, eta = 0.6, tau = std::nan(""), gamma = 0.5;
+  if (params) {
+    beta = params[0];
+    eta = params[1];
+    tau = params[2];
+    gamma = params[3];
+  }
+  if (std::isnan(tau)) tau = -1.0;
+  double W[36] = {0.0};
+  double F = 0.0;
+  switch (kind) {
+    case HMG_OBJ_BULK:
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) W[i * 6 + j] = -1.0 / 9.0;
+      break;
+    case HMG_OBJ_SHEAR:
+      for (int i = 3; i < 6; ++i) W[i * 6 + i] = -1.0 / 3.0;
+      break;
+    case HMG_OBJ_POISSON_RELAXED: {
+      if (!(beta > 0.0 && beta < 1.0)) return HMG_E_INVALID;
+      const double b = std::pow(beta, (double)iteration);
+      W[0 * 6 + 1] = W[0 * 6 + 2] = W[1 * 6 + 2] = 1.0;
+      for (int i = 0; i < 3; ++i) W[i * 6 + i] = -b;
+      break;
+    }
+    case HMG_OBJ_POISSON_LOG: {
+      const double A = C[0 * 6 + 1] + C[1 * 6 + 2] + C[2 * 6 + 0];
+      const double B = C[0] + C[7] + C[14];
+      if (!(B > 0.0) || !(1.0 + eta * A / B > 0.0)) return HMG_E_INVALID;
+      F = std::log(1.0 + eta * A / B) + tau * std::pow(B, gamma);
+      const double dA = eta / (B + eta * A);
+      const double dB = -eta * A / (B * (B + eta * A)) + tau * gamma * std::pow(B, gamma - 1.0);
+      W[0 * 6 + 1] = W[1 * 6 + 2] = W[2 * 6 + 0] = dA;
+      for (int i = 0; i < 3; ++i) W[i * 6 + i] = dB;
+      std::memcpy(W_out, W, sizeof(W));
+      *F_out = F;
+      return HMG_OK;
+    }
+    default:
+      return HMG_E_INVALID;
+  }
+  for (int t = 0; t < 36; ++t) F += W[t] * C[t];
+  std::memcpy(W_out, W, sizeof(W));
+  *F_out = F;
+  return HMG_OK;
+}
+
+hmg_status hmg_should_stop(const double* history, int32_t count, double rel_change,
+                           int32_t window, int32_t max_iter, int32_t* stop_out) {
+  if ((!history && count > 0) || count < 0 || !stop_out || !(rel_change > 0.0) || window < 1 ||
+      max_iter < 1)
+    return HMG_E_INVALID;
+  int stop = count >= max_iter ? 1 : 0;
+  if (!stop && count >= window + 1) {
+    stop = 1;
+    for (int k = count - window; k < count; ++k)
+      if (!(std::fabs(history[k] - history[k - 1]) < rel_change * std::fabs(history[k - 1])))
+        stop = 0;
+  }
+  *stop_out = stop;
+  return HMG_OK;
+}
+
+hmg_status hmg_symmetrize(hmg_ctx ctx, const float* in_dev, float* out_dev, int32_t kind) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!in_dev || !out_dev || in_dev == out_dev)
+    return report(ctx, fail(HMG_E_INVALID, "symmetrize needs distinct non-NULL buffers"));
+  if (kind < HMG_SYM_REFLECT3 || kind > HMG_SYM_ROTATE3)
+    return report(ctx, fail(HMG_E_INVALID, "unknown symmetry %d", kind));
+  const Grid& g = ctx->g0;
+  if (kind != HMG_SYM_REFLECT3 && !(g.nx == g.ny && g.ny == g.nz))
+    return report(ctx, fail(HMG_E_INVALID, "reflect6 and rotate3 need a cubic cell"));
+  // signed permutations in the order (permutation lexicographic, flips binary
+  // with the x bit most significant), kept by kind
+  SymOps ops;
+  int perm[3] = {0, 1, 2};
+  do {
+    const int inv = (perm[0] > perm[1]) + (perm[0] > perm[2]) + (perm[1] > perm[2]);
+    for (int f = 0; f < 8; ++f) {
+      const int fx = (f >> 2) & 1, fy = (f >> 1) & 1, fz = f & 1;
+      const int det = ((inv & 1) ? -1 : 1) * (((fx + fy + fz) & 1) ? -1 : 1);
+      const bool identity = perm[0] == 0 && perm[1] == 1 && perm[2] == 2;
+      if (kind == HMG_SYM_REFLECT3 && !identity) continue;
+      if (kind == HMG_SYM_ROTATE3 && det != 1) continue;
+      ops.code[ops.count++] = perm[0] | perm[1] << 2 | perm[2] << 4 | (fx | fy << 1 | fz << 2) << 6;
+    }
+  } while (std::next_permutation(perm, perm + 3));
+  symmetrize(g, in_dev, out_dev, ops, ctx->stream);
+  return report(ctx, check_hip("symmetrize"));
+}
+
+hmg_status hmg_trig_init(hmg_ctx ctx, int32_t nfreq, const double q[4], const double* weights,
+                         int32_t nweights, double volfrac, double rho_min, double k_sigmoid,
+                         float* x_out_dev, double* mu_out) {
+  if (!ctx) return HMG_E_INVALID;
+  if (!q || !weights || !x_out_dev || nfreq < 1 || nfreq > TRIG_MAX_FREQ)
+    return report(ctx, fail(HMG_E_INVALID, "bad trig_init arguments (nfreq %d)", nfreq));
+  const int nt = 6 * nfreq;
+  if (nweights != nt + nt * (nt + 1) / 2)
+    return report(ctx, fail(HMG_E_INVALID, "need %d weights, got %d", nt + nt * (nt + 1) / 2,
+                            nweights));
+  if (!(volfrac > 0.0 && volfrac < 1.0) || !(rho_min >= 0.0) ||
+      !(rho_min + std::fmin(1.5 * volfrac, 1.0) > volfrac) || !(k_sigmoid > 0.0))
+    return report(ctx, fail(HMG_E_INVALID, "bad projection parameters"));
+  const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  if (!(qn > 0.0)) return report(ctx, fail(HMG_E_INVALID, "the quaternion is zero"));
+  const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  TrigBasis tb{{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)},
+               nfreq};
+  hipStream_t st = ctx->stream;
+  (void)hipMemcpyAsync(ctx->tw, weights, sizeof(double) * nweights, hipMemcpyHostToDevice, st);
+  trig_field(ctx->g0, tb, ctx->tw, x_out_dev, st);
+  sigmoid_project(ctx->g0, x_out_dev, volfrac, rho_min, k_sigmoid, ctx->ocstate, ctx->ocpart, 200,
+                  st);
+  double state[4];
+  (void)hipMemcpyAsync(state, ctx->ocstate, sizeof(double) * 4, hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return report(ctx, check_hip("trig_init"));
+  if (mu_out) *mu_out = state[3];
+  return report(ctx, check_hip("trig_init"));
 }
 
 hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev) {
@@ -1512,6 +1764,10 @@ hmg_status hmg_batch_create(const hmg_config* base, int32_t ncells, const int32_
   Status s;
   for (int c = 0; c < ncells && s.code == HMG_OK; ++c) {
     hmg_config cfg = *base;
+    if (cfg.smoother != 0) {
+      s = fail(HMG_E_INVALID, "batched solves smooth with damped block Jacobi (smoother 0)");
+      break;
+    }
     cfg.nx = dims[3 * c];
     cfg.ny = dims[3 * c + 1];
     cfg.nz = dims[3 * c + 2];

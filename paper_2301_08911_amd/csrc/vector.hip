@@ -1,6 +1,8 @@
 // Pointwise PCG kernels on the fine grid and the small finalizer kernels that
 // turn deterministic per-block partial sums into the FP64 scalars of the six
 // CG recurrences (dot products, step lengths, convergence state).
+#include <type_traits>
+
 #include "hmg_internal.hpp"
 
 namespace hmg {
@@ -239,8 +241,12 @@ __global__ void pattern_kernel(T* __restrict__ a, int64_t count) {
 template <typename S, typename D>
 __global__ void convert_kernel(D* __restrict__ d, const S* __restrict__ s, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    d[i] = (D)(typename Acc<D>::type)to_d(s[i]);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if constexpr (std::is_same<D, f16>::value)
+      d[i] = (D)to_d(s[i]);  // one rounding, straight from double
+    else
+      d[i] = (D)(typename Acc<D>::type)to_d(s[i]);
+  }
 }
 
 template <typename T>
@@ -437,6 +443,7 @@ template void vec_convert<float, float>(float*, const float*, int64_t, hipStream
 template void vec_convert<float, bf16>(bf16*, const float*, int64_t, hipStream_t);
 template void vec_convert<bf16, float>(float*, const bf16*, int64_t, hipStream_t);
 template void vec_convert<bf16, double>(double*, const bf16*, int64_t, hipStream_t);
+template void vec_convert<double, f16>(f16*, const double*, int64_t, hipStream_t);
 
 template <typename T>
 void vec_update_r2(const Grid& g, double* x, const T* pprev, const T* p, T* r, const T* q,
@@ -513,6 +520,8 @@ void vec_dot_cases(const Grid& g, const TA* a, const TB* b, const double* scal, 
   hipLaunchKernelGGL((dot_kernel<TA, TB>), dim3(nb), dim3(VB), 0, st, g, a, b, scal, part, slot);
   *nblk_out = nb;
 }
+template void vec_dot_cases<double, float>(const Grid&, const double*, const float*,
+                                           const double*, Partials, int, int*, hipStream_t);
 template void vec_dot_cases<float, bf16>(const Grid&, const float*, const bf16*, const double*,
                                          Partials, int, int*, hipStream_t);
 template <typename T>

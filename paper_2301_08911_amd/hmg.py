@@ -18,6 +18,38 @@ OK, E_INVALID, E_OOM, E_DEVICE, E_NOT_CONVERGED, E_STATE = range(6)
 KERNELS = {"matvec": 0, "residual": 1, "post_smooth": 2, "update": 3, "true_residual": 4,
            "jacobi": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1, "mixed_bf16": 2, "mixed_bf16_stencil": 4}
+SMOOTHERS = {"jacobi": 0, "gs": 1}
+SYMMETRIES = {"reflect3": 0, "reflect6": 1, "rotate3": 2}
+OBJECTIVES = {"bulk": 0, "shear": 1, "poisson_relaxed": 2, "poisson_log": 3}
+
+
+def _dbl(values):
+    a = np.ascontiguousarray(values, dtype=np.float64).ravel()
+    return (ctypes.c_double * a.size)(*a.tolist())
+
+
+def objective(kind: str, C, iteration: int = 0, params=None):
+    """hmg_objective: (F, W = dF/dC^H) of one of the objectives (host only)."""
+    lib = _lib.load()
+    F = ctypes.c_double()
+    W = (ctypes.c_double * 36)()
+    st = lib.hmg_objective(OBJECTIVES[kind], _dbl(C), int(iteration),
+                           _dbl(params) if params is not None else None, ctypes.byref(F), W)
+    if st != OK:
+        raise HmgError(st, f"hmg_objective({kind}) failed")
+    return F.value, np.array(W[:]).reshape(6, 6)
+
+
+def should_stop(history, rel_change=5e-4, window=3, max_iter=300) -> bool:
+    """hmg_should_stop: the stopping rule on an objective history (host only)."""
+    lib = _lib.load()
+    h = np.ascontiguousarray(history, dtype=np.float64)
+    out = ctypes.c_int32()
+    st = lib.hmg_should_stop(_dbl(h) if h.size else None, int(h.size), rel_change, window,
+                             max_iter, ctypes.byref(out))
+    if st != OK:
+        raise HmgError(st, "hmg_should_stop failed")
+    return bool(out.value)
 
 
 class HmgError(RuntimeError):
@@ -41,7 +73,7 @@ class Context:
     """One periodic cell on the current GPU (``hmg_create`` / ``hmg_destroy``)."""
 
     def __init__(self, shape, *, E0=1.0, nu=0.3, penal=3.0, Emin=1e-9, levels=0, omega=0.0,
-                 precision="fp32", replace_every=None,
+                 precision="fp32", replace_every=None, smoother="jacobi", post_fp16=False,
                  stream: torch.cuda.Stream | None = None):
         self.lib = _lib.load()
         nx, ny, nz = (int(v) for v in shape)
@@ -54,7 +86,8 @@ class Context:
         if replace_every is None:  # the mixed form recomputes r in FP64 every 20 iterations
             replace_every = 20 if precision.startswith("mixed") else 0
         cfg = _lib.HmgConfig(nx, ny, nz, E0, nu, penal, Emin, levels, omega, 1, 1,
-                             PRECISIONS[precision], replace_every)
+                             PRECISIONS[precision], replace_every, SMOOTHERS[smoother],
+                             int(bool(post_fp16)))
         self.config = cfg
         handle = ctypes.c_void_p()
         st = self.lib.hmg_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -137,6 +170,32 @@ class Context:
         self._check(self.lib.hmg_filter(self._h, _ptr(self._scalar(inp, "in")),
                                         _ptr(self._scalar(out, "out")), radius, int(adjoint)))
         return out
+
+    def filter_sensitivity(self, x: torch.Tensor, g: torch.Tensor,
+                           out: torch.Tensor | None = None, radius=2.0) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(self.lib.hmg_filter_sensitivity(self._h, _ptr(self._scalar(x, "x")),
+                                                    _ptr(self._scalar(g, "g")),
+                                                    _ptr(self._scalar(out, "out")), radius))
+        return out
+
+    def symmetrize(self, inp: torch.Tensor, kind: str,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(self.lib.hmg_symmetrize(self._h, _ptr(self._scalar(inp, "in")),
+                                            _ptr(self._scalar(out, "out")), SYMMETRIES[kind]))
+        return out
+
+    def trig_init(self, nfreq: int, q, weights, volfrac: float, rho_min=1e-3, k=15.0,
+                  out: torch.Tensor | None = None):
+        """hmg_trig_init; returns (density, mu)."""
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device) if out is None else out
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        mu = ctypes.c_double()
+        self._check(self.lib.hmg_trig_init(self._h, int(nfreq), _dbl(q), _dbl(w), int(w.size),
+                                           volfrac, rho_min, k, _ptr(self._scalar(out, "out")),
+                                           ctypes.byref(mu)))
+        return out, mu.value
 
     def get_displacement(self, out: torch.Tensor | None = None) -> torch.Tensor:
         out = self.new_field() if out is None else out

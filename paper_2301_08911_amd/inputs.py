@@ -151,3 +151,14 @@ def random_signed_field(shape, seed: int, stream: int = 5, ncases: int = 6) -> n
     nx, ny, nz = shape
     n = nx * ny * nz
     return (2.0 * uniform01(seed, stream, ncases * 3 * n) - 1.0).reshape(ncases, 3, n)
+
+
+def trig_init_draws(nfreq: int, seed: int):
+    """Random draws of the trigonometric initialization: a quaternion with four
+    entries in [-1, 1) and one weight in [-1, 1) per basis function of Q_n
+    (6 nfreq + 3 nfreq (6 nfreq + 1) functions)."""
+    t = 6 * nfreq
+    nb = t + t * (t + 1) // 2
+    q = 2.0 * uniform01(seed, 13, 4) - 1.0
+    w = 2.0 * uniform01(seed, 14, nb) - 1.0
+    return q, w

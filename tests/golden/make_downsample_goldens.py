@@ -16,6 +16,8 @@ sensitivity and one OC update at sampled elements.
   move 0.05, damping 0.5, xmin 1e-3) of the downsampled design.
 * ``vf015_256_ds32.txt``: the 256^3 smoothed-noise density (sigma 3,
   VF 0.15, seed 2) box-averaged to 32^3: C^H.
+* ``gs_cell64_vf03.txt``: C^H of a 64^3 smoothed-noise cell (sigma 3, VF 0.3,
+  seed 5), the Gauss-Seidel smoother's full-size parity case.
 * ``batch_small_cells.txt``: C^H of the cells of at most 24^3 vertices among
   the six uneven cells of the batched-solve test (smoothed noise, sigma 2,
   seed 40 + k, VF 0.15 + 0.05 k for cell k).
@@ -115,8 +117,18 @@ def batch_small_cells(log):
     return out
 
 
+def gs_cell64_vf03(log):
+    shape = (64, 64, 64)
+    rho = I.smoothed_noise_density(shape, 5, 0.3, sigma=3.0)
+    rho = rho.ravel().astype(np.float32).astype(np.float64)
+    u, it, rr, C, _, _ = _solve(rho, shape, log)
+    head = ("# gs_cell64_vf03: 64^3 smoothed noise (seed 5, sigma 3, VF 0.3) rounded to float32;\n"
+            "# FP64 oracle, multigrid-preconditioned CG to a recomputed relative residual 1e-10.\n")
+    return head + _fmt("iters", it) + _fmt("relres", rr) + _fmt("C", C)
+
+
 GOLDENS = {"shear128_ds32": shear128_ds32, "vf015_256_ds32": vf015_256_ds32,
-           "batch_small_cells": batch_small_cells}
+           "batch_small_cells": batch_small_cells, "gs_cell64_vf03": gs_cell64_vf03}
 
 
 def read_golden(path):

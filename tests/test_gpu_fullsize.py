@@ -116,6 +116,13 @@ def test_batch48_sampled_cells_match_single_solves():
     Cb = b.elastic_tensors()
     conv = r.relres.max(axis=1) <= 1e-6
     print("converged cells", int(conv.sum()), flush=True)
+    # Known limit of the damped-Jacobi V-cycle: near-percolation 128^3 cells
+    # (VF below 0.16) need more than 3000 iterations; every other cell converges.
+    stuck = [k for k in range(48) if not conv[k]]
+    print("unconverged cells", [(k, shapes[k][0], round(float(vfs[k]), 3)) for k in stuck],
+          flush=True)
+    assert all(shapes[k][0] == 128 and vfs[k] < 0.16 for k in stuck), stuck
+    assert int(conv.sum()) >= 45
     # sampled converged cells of every size present
     chosen = []
     for sz in sizes:
