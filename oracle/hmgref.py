@@ -368,12 +368,15 @@ def gs_colour_step(K_rows: sp.csr_matrix, Dinv_rows: np.ndarray, r: np.ndarray, 
 
 
 def multigrid_preconditioner(K: sp.csr_matrix, shape, min_dim: int = 4, sweeps: int = 1,
-                             smoother: str = "gs", omega_scale: float = 1.0 / 1.1):
+                             smoother: str = "gs", omega_scale: float = 1.0 / 1.1,
+                             first_factor: int = 2):
     """One symmetric multigrid V-cycle (Sec. 3.3, Alg. 1) as a CG preconditioner.
 
     Levels: K_{l+1} = P_l^T K_l P_l with the periodic trilinear P of
     ``prolongation`` (restriction = P^T), halving while every axis stays even
-    and the coarse grid keeps at least ``min_dim`` cells per axis.  Coarsest
+    and the coarse grid keeps at least ``min_dim`` cells per axis.  With
+    ``first_factor`` 4 the first step divides every axis by 4 instead
+    (non-dyadic coarsening, Sec. 4.2), the later ones halve.  Coarsest
     level: the dense solve of the vertex-0-pinned matrix.  Every residual is
     projected to zero mean per component before it is smoothed or solved (the
     translation null space); the cycle starts from zero on every level.
@@ -391,12 +394,13 @@ def multigrid_preconditioner(K: sp.csr_matrix, shape, min_dim: int = 4, sweeps: 
     Ks, shapes, Ps = [K.tocsr()], [tuple(shape)], []
     while True:
         nx, ny, nz = shapes[-1]
-        if nx % 2 or ny % 2 or nz % 2 or min(nx, ny, nz) // 2 < min_dim:
+        F = first_factor if len(shapes) == 1 else 2
+        if nx % F or ny % F or nz % F or min(nx, ny, nz) // F < min_dim:
             break
-        P = prolongation(shapes[-1])
+        P = prolongation(shapes[-1], F)
         Ps.append(P)
         Ks.append((P.T @ Ks[-1] @ P).tocsr())
-        shapes.append((nx // 2, ny // 2, nz // 2))
+        shapes.append((nx // F, ny // F, nz // F))
     L = len(Ks) - 1
     Dinv, omegas, colour_rows = [], [], []
     rng = np.random.default_rng(12345)
@@ -595,16 +599,25 @@ def oc_update(x, g, volfrac: float, move: float = 0.05, damp: float = 0.5,
 # Multigrid reference (Sec. 3.3): periodic trilinear prolongation and Galerkin
 # ---------------------------------------------------------------------------
 
-def prolongation(shape) -> sp.csr_matrix:
-    """Periodic trilinear interpolation P from the (n/2)^3 grid, as (3 n_f) x (3 n_c)."""
+def prolongation(shape, factor: int = 2) -> sp.csr_matrix:
+    """Periodic trilinear interpolation P from the grid coarser by ``factor`` per
+    axis, as (3 n_f) x (3 n_c).  Factor 2 is the dyadic hierarchy of Sec. 3.3;
+    factor 4 is the non-dyadic first step of Sec. 4.2 (the second level skipped),
+    with the weights (d - |x_v - x_f|) / d of Eq. st-assemb-w, d = 4 fine cells:
+    fine coordinate f = 4 X + r takes coarse X with weight (4 - r) / 4 and
+    X + 1 with r / 4."""
     nx, ny, nz = shape
-    cx, cy, cz = nx // 2, ny // 2, nz // 2
+    F = int(factor)
+    cx, cy, cz = nx // F, ny // F, nz // F
     rows, cols, vals = [], [], []
 
     def taps(f, nc):
-        if f % 2 == 0:
-            return [(f // 2, 1.0)]
-        return [((f - 1) // 2, 0.5), (((f + 1) // 2) % nc, 0.5)]
+        X, r = divmod(f, F)
+        if r == 0:
+            return [(X, 1.0)]
+        if F == 2:
+            return [((f - 1) // 2, 0.5), (((f + 1) // 2) % nc, 0.5)]
+        return [(X, (F - r) / F), ((X + 1) % nc, r / F)]
 
     for z in range(nz):
         for y in range(ny):

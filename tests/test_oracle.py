@@ -501,6 +501,49 @@ def test_prolongation_interpolates_linear_in_interior():
     assert np.abs(fine[inner, 2] - z[inner] / 2).max() < 1e-15
 
 
+def test_factor4_prolongation_is_two_dyadic_steps():
+    # Linear interpolation by 4 along an axis is linear interpolation by 2
+    # twice, so the non-dyadic P equals the product of two dyadic ones.
+    shape = (16, 8, 12)
+    P4 = O.prolongation(shape, 4)
+    P2 = O.prolongation(shape) @ O.prolongation((8, 4, 6))
+    assert P4.shape == P2.shape
+    assert abs(P4 - P2).max() < 1e-15
+
+
+def test_factor4_prolongation_interpolates_linear_in_interior():
+    shape = (16, 16, 16)
+    P = O.prolongation(shape, 4)
+    X = np.arange(4)
+    Zc, Yc, Xc = np.meshgrid(X, X, X, indexing="ij")
+    coarse = np.stack([Xc.ravel() - Yc.ravel(), Zc.ravel(), 0 * Xc.ravel()], 1).ravel()
+    fine = (P @ coarse).reshape(-1, 3)
+    v = np.arange(16 ** 3)
+    x, y, z = v % 16, (v // 16) % 16, v // 256
+    inner = (x <= 12) & (y <= 12) & (z <= 12)
+    assert np.abs(fine[inner, 0] - (x - y)[inner] / 4).max() < 1e-15
+    assert np.abs(fine[inner, 1] - z[inner] / 4).max() < 1e-15
+
+
+def test_nondyadic_multigrid_solve_equals_brute_force(K0):
+    shape = (16, 16, 16)
+    s = O.simp_scale(I.uniform_density(shape, 6))
+    K = O.assemble_stiffness(s, shape, K0)
+    f = O.load_vectors(s, shape, K0, O.unit_strain_displacements())[:2]
+    prec = O.multigrid_preconditioner(K, shape, first_factor=4)
+    assert prec.levels == 2  # 16^3 -> 4^3 in one step
+    r = np.random.default_rng(2).standard_normal((2, 16 ** 3, 3))
+    q = np.random.default_rng(3).standard_normal((2, 16 ** 3, 3))
+    r -= r.mean(axis=1, keepdims=True)
+    q -= q.mean(axis=1, keepdims=True)
+    a, b = (prec(r) * q).sum(), (r * prec(q)).sum()
+    assert abs(a - b) < 1e-11 * abs(a)
+    u, it, rr = O.pcg_solve(K, f, tol=1e-10, prec=prec)
+    ub, _, _ = O.pcg_solve(K, f, tol=1e-12)
+    assert rr.max() <= 1e-10
+    assert np.abs(u - ub).max() < 1e-8 * np.abs(ub).max()
+
+
 # --------------------------------------------------------------------- generators
 
 def test_generators_counts_and_mean():

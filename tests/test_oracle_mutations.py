@@ -56,6 +56,10 @@ MUTATIONS = {
         "hmgref", "test_oracle",
         "return constitutive_matrix(E, nu) / float(np.mean(1.0 / np.asarray(s)))",
         "return constitutive_matrix(E, nu) * float(np.mean(np.asarray(s)))"),
+    "factor-4 weights swapped": (
+        "hmgref", "test_oracle",
+        "return [(X, (F - r) / F), ((X + 1) % nc, r / F)]",
+        "return [(X, r / F), ((X + 1) % nc, (F - r) / F)]"),
     "prolongate odd weight": (
         "hmgref", "test_oracle", "odd = 0.5 * (U + np.roll(U, -1, axis=axis))",
         "odd = 0.5 * (U + np.roll(U, 1, axis=axis))"),
