@@ -116,6 +116,13 @@ typedef struct hmg_config {
                              C^H is second order in the rounding (the
                              residual vanishes), the sensitivities first
                              order (about 1e-3 relative)                      */
+  int32_t nondyadic;      /* 1 = the first coarsening divides every axis by 4
+                             (Sec. 4.2 non-dyadic coarsening: the stencil goes
+                             from the first level straight to the third, which
+                             saves the largest stored stencil); later steps
+                             halve.  Needs every axis divisible by 4 and
+                             >= 16.  Transfers to and from that level use the
+                             weights (4 - |a|)/4 of Eq. (st-assemb-w)         */
 } hmg_config;
 
 /* Create a context for one cell on the current HIP device.  `hip_stream` is a

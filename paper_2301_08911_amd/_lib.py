@@ -32,7 +32,7 @@ class HmgConfig(ctypes.Structure):
         ("Emin", ctypes.c_double), ("levels", ctypes.c_int32), ("omega", ctypes.c_double),
         ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("replace_every", ctypes.c_int32), ("smoother", ctypes.c_int32),
-        ("post_fp16", ctypes.c_int32),
+        ("post_fp16", ctypes.c_int32), ("nondyadic", ctypes.c_int32),
     ]
 
 

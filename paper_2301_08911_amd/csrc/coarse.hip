@@ -401,12 +401,93 @@ __global__ void prolong_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __
   }
 }
 
-// First coarse level from the densities.  Coarse vertex V is local node A of
-// the coarse element with origin V - A; that element holds the 8 fine elements
-// 2(V - A) + sigma, each contributing s * (W_sigma^T K0 W_sigma)[A, A + D].
+// Non-dyadic first step (Sec. 4.2): the coarse grid is 4 times coarser per
+// axis and the trilinear weights along an axis are (4 - |a|)/4, |a| <= 3
+// (Eq. st-assemb-w with the coarse element 4 fine cells long).
+__device__ __forceinline__ double w4(int a) { return (4 - (a < 0 ? -a : a)) * 0.25; }
+
+// Restriction R = P^T for the factor-4 step: rc[V] = sum_a w4(a) tf[4V + a]
+// over a in {-3..3}^3.  A thread per coarse vertex and load case; the fine
+// rows 4Y + ay, 4Z + az are visited in turn.
+template <typename T>
+__global__ void restrict4_kernel(Grid gf, Grid gc, const T* __restrict__ tf, T* __restrict__ rc,
+                                 const double* scal) {
+  using A = typename Acc<T>::type;
+  const int c = blockIdx.y;
+  if (!case_on(scal, c)) return;
+  for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < gc.n;
+       V += (int64_t)gridDim.x * blockDim.x) {
+    const int X = (int)(V % gc.nx);
+    const int Y = (int)((V / gc.nx) % gc.ny);
+    const int Z = (int)(V / ((int64_t)gc.nx * gc.ny));
+    A acc[3] = {A(0), A(0), A(0)};
+    for (int az = -3; az <= 3; ++az) {
+      const int z = modp(4 * Z + az, gf.nz);
+      for (int ay = -3; ay <= 3; ++ay) {
+        const int y = modp(4 * Y + ay, gf.ny);
+        const A wyz = (A)(w4(ay) * w4(az));
+        const int64_t rb = (int64_t)gf.nx * (y + (int64_t)gf.ny * z);
+#pragma unroll
+        for (int ax = -3; ax <= 3; ++ax) {
+          const int x = modp(4 * X + ax, gf.nx);
+          const A w = wyz * (A)w4(ax);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) acc[k] += w * (A)tf[(int64_t)(c * 3 + k) * gf.n + rb + x];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rc[(int64_t)(c * 3 + k) * gc.n + V] = (T)acc[k];
+  }
+}
+
+// Prolongation P for the factor-4 step: fine coordinate 4X + r takes coarse X
+// with weight (4 - r)/4 and X + 1 with r/4, axis by axis.  A thread per fine
+// vertex and load case.
+template <typename T, typename C, bool OVERWRITE>
+__global__ void prolong4_kernel(Grid gf, Grid gc, T* __restrict__ zf, const C* __restrict__ ec,
+                                const double* scal) {
+  using A = typename Acc<T>::type;
+  const int c = blockIdx.y;
+  if (!case_on(scal, c)) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < gf.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(v % gf.nx);
+    const int y = (int)((v / gf.nx) % gf.ny);
+    const int z = (int)(v / ((int64_t)gf.nx * gf.ny));
+    const int X0 = x >> 2, Y0 = y >> 2, Z0 = z >> 2;
+    const int rx = x & 3, ry = y & 3, rz = z & 3;
+    const int X1 = X0 + 1 == gc.nx ? 0 : X0 + 1;
+    const int Y1 = Y0 + 1 == gc.ny ? 0 : Y0 + 1;
+    const int Z1 = Z0 + 1 == gc.nz ? 0 : Z0 + 1;
+    const A wx[2] = {A(4 - rx) * A(0.25), A(rx) * A(0.25)};
+    const A wy[2] = {A(4 - ry) * A(0.25), A(ry) * A(0.25)};
+    const A wz[2] = {A(4 - rz) * A(0.25), A(rz) * A(0.25)};
+    const int Xs[2] = {X0, X1}, Ys[2] = {Y0, Y1}, Zs[2] = {Z0, Z1};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const C* e = ec + (int64_t)(c * 3 + k) * gc.n;
+      A acc = A(0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int qx = q & 1, qy = (q >> 1) & 1, qz = q >> 2;
+        acc += wx[qx] * wy[qy] * wz[qz] *
+               (A)e[Xs[qx] + (int64_t)gc.nx * (Ys[qy] + (int64_t)gc.ny * Zs[qz])];
+      }
+      T* o = zf + (int64_t)(c * 3 + k) * gf.n + v;
+      *o = OVERWRITE ? (T)acc : (T)((A)*o + acc);
+    }
+  }
+}
+
+// First coarse level from the densities, for a coarse grid F = 2 or 4 times
+// coarser per axis.  Coarse vertex V is local node A of the coarse element with
+// origin V - A; that element holds the F^3 fine elements F(V - A) + sigma, each
+// contributing s * (W_sigma^T K0 W_sigma)[A, A + D] (msig: F^3 matrices 24x24).
 template <typename S, typename T>
 __global__ void galerkin_first_kernel(Grid gf, Grid gc, const S* __restrict__ s,
                                       const double* __restrict__ msig, T* __restrict__ st) {
+  const int F = gf.nx / gc.nx;
   const int d = blockIdx.y;
   const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
   for (int64_t V = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; V < gc.n;
@@ -421,10 +502,10 @@ __global__ void galerkin_first_kernel(Grid gf, Grid gc, const S* __restrict__ s,
       if (B0 < 0 || B0 > 1 || B1 < 0 || B1 > 1 || B2 < 0 || B2 > 1) continue;
       const int B = B0 + 2 * B1 + 4 * B2;
       const int CX = modp(X - A0, gc.nx), CY = modp(Y - A1, gc.ny), CZ = modp(Z - A2, gc.nz);
-      for (int sg = 0; sg < 8; ++sg) {
-        const int64_t e = (2 * CX + (sg & 1)) +
-                          (int64_t)gf.nx * ((2 * CY + ((sg >> 1) & 1)) +
-                                            (int64_t)gf.ny * (2 * CZ + (sg >> 2)));
+      for (int sg = 0; sg < F * F * F; ++sg) {
+        const int sx = sg % F, sy = (sg / F) % F, sz = sg / (F * F);
+        const int64_t e = (F * CX + sx) +
+                          (int64_t)gf.nx * ((F * CY + sy) + (int64_t)gf.ny * (F * CZ + sz));
         const double se = (double)s[e];
         const double* M = msig + (int64_t)sg * 576;
 #pragma unroll
@@ -662,15 +743,31 @@ void kc_smooth(const Grid& g, const W* st, const T* z, const T* r, const W* dinv
                        g, st, z, r, dinv, zout, scal, mean);
 }
 
+inline bool factor4(const Grid& gf, const Grid& gc) { return gf.nx == 4 * gc.nx; }
+
 template <typename T>
 void restrict_to(const Grid& gf, const Grid& gc, const T* tf, T* rc, const double* scal,
                  hipStream_t s) {
+  if (factor4(gf, gc)) {
+    hipLaunchKernelGGL(restrict4_kernel<T>, dim3(pw_blocks(gc.n, 256, 4096), NCASE), dim3(256), 0,
+                       s, gf, gc, tf, rc, scal);
+    return;
+  }
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(gc.ny * gc.nz, NCASE), dim3(row_threads(gc.nx)), 0,
                      s, gf, gc, tf, rc, scal);
 }
 template <typename T, typename C>
 void prolong_add(const Grid& gf, const Grid& gc, T* zf, const C* ec, const double* scal,
                  bool overwrite, hipStream_t s) {
+  if (factor4(gf, gc)) {
+    if (overwrite)
+      hipLaunchKernelGGL((prolong4_kernel<T, C, true>), dim3(pw_blocks(gf.n, 256, 8192), NCASE),
+                         dim3(256), 0, s, gf, gc, zf, ec, scal);
+    else
+      hipLaunchKernelGGL((prolong4_kernel<T, C, false>), dim3(pw_blocks(gf.n, 256, 8192), NCASE),
+                         dim3(256), 0, s, gf, gc, zf, ec, scal);
+    return;
+  }
   if (overwrite)
     hipLaunchKernelGGL((prolong_kernel<T, C, true>), dim3(gf.ny * gf.nz, NCASE),
                        dim3(row_threads(gc.nx)), 0, s, gf, gc, zf, ec, scal);

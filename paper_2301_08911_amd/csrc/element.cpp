@@ -234,32 +234,40 @@ int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen
     out->lam0 = lam;
   }
 
-  // ---- sub-element Galerkin matrices: fine element at sub-position sigma of
-  // a coarse element; its node b sits at xi = (sigma + b)/2 in coarse-element
-  // coordinates and takes trilinear weights of the coarse nodes A.
-  for (int sg = 0; sg < 8; ++sg) {
+  // ---- sub-element Galerkin matrices of the dyadic first coarse level
+  subelement_matrices(out->K0, 2, &out->msig[0][0][0]);
+  return 0;
+}
+
+// Fine element at sub-position sigma = (sx, sy, sz) in 0..F-1 of a coarse
+// element F fine cells long; its node b sits at xi = (sigma + b) / F in
+// coarse-element coordinates and takes the trilinear weights of the coarse
+// nodes A (Eq. st-assemb-w).  Matrix sigma = sx + F (sy + F sz) is
+// W_sigma^T K0 W_sigma, 24 x 24 row-major.
+void subelement_matrices(const double K0[24][24], int F, double* out) {
+  for (int sg = 0; sg < F * F * F; ++sg) {
+    const int sub[3] = {sg % F, (sg / F) % F, sg / (F * F)};
     double w[8][8];
     for (int b = 0; b < 8; ++b)
       for (int A = 0; A < 8; ++A) {
         double v = 1.0;
         for (int t = 0; t < 3; ++t) {
-          const double xi = 0.5 * (bit(sg, t) + bit(b, t));
+          const double xi = (double)(sub[t] + bit(b, t)) / F;
           v *= bit(A, t) ? xi : 1.0 - xi;
         }
         w[b][A] = v;
       }
+    double* M = out + (size_t)sg * 576;
     for (int A = 0; A < 8; ++A)
       for (int Bn = 0; Bn < 8; ++Bn)
         for (int p = 0; p < 3; ++p)
           for (int q = 0; q < 3; ++q) {
             double acc = 0.0;
             for (int a = 0; a < 8; ++a)
-              for (int b = 0; b < 8; ++b)
-                acc += w[a][A] * out->K0[3 * a + p][3 * b + q] * w[b][Bn];
-            out->msig[sg][3 * A + p][3 * Bn + q] = acc;
+              for (int b = 0; b < 8; ++b) acc += w[a][A] * K0[3 * a + p][3 * b + q] * w[b][Bn];
+            M[(3 * A + p) * 24 + 3 * Bn + q] = acc;
           }
   }
-  return 0;
 }
 
 }  // namespace hmg

@@ -96,6 +96,10 @@ struct ElementConsts {
 
 // Returns 0 on success; fills `err` otherwise.
 int build_element_consts(double nu, ElementConsts* out, char* err, size_t errlen);
+// The F^3 sub-element Galerkin matrices W_sigma^T K0 W_sigma of a coarse
+// element F fine cells long (F = 2: ElementConsts::msig; F = 4: the
+// non-dyadic first step), F^3 x 576 doubles.
+void subelement_matrices(const double K0[24][24], int F, double* out);
 
 // Scalar slots of the PCG state, stored as double scal[slot * 8 + case].
 enum Slot {

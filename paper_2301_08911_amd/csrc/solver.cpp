@@ -284,6 +284,15 @@ class Solver final : public SolverIface {
     (void)hipMemcpyAsync(K0dev_, &ec_.K0[0][0], sizeof(double) * 576, hipMemcpyHostToDevice, st_);
     (void)hipMemcpyAsync(msig_, &ec_.msig[0][0][0], sizeof(double) * 8 * 576, hipMemcpyHostToDevice,
                    st_);
+    if (L > 1 && grids_[0].nx == 4 * grids_[1].nx) {
+      // non-dyadic first step: 64 sub-element matrices
+      msig4_host_.assign(64 * 576, 0.0);
+      subelement_matrices(ec_.K0, 4, msig4_host_.data());
+      msig4_ = (double*)A(sizeof(double) * 64 * 576);
+      if (!msig4_) return fail(HMG_E_OOM, "device allocation failed (sub-element matrices)");
+      (void)hipMemcpyAsync(msig4_, msig4_host_.data(), sizeof(double) * 64 * 576,
+                           hipMemcpyHostToDevice, st_);
+    }
 
     vec_fill<double>(x_, F, 0.0, st_);
     HMG_TRY(check_hip("init"));
@@ -423,7 +432,7 @@ class Solver final : public SolverIface {
     if (!gs_) dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
     for (int l = 1; l < L; ++l) {
       if (l == 1)
-        galerkin_first<T, W>(g0, grids_[1], s_, msig_, lev_[1].st, st_);
+        galerkin_first<T, W>(g0, grids_[1], s_, msig4_ ? msig4_ : msig_, lev_[1].st, st_);
       else
         galerkin_next<W>(grids_[l - 1], grids_[l], lev_[l - 1].st, lev_[l].st, st_);
       if (l == L - 1) continue;  // the coarsest level is solved directly
@@ -927,6 +936,8 @@ class Solver final : public SolverIface {
   int stride_ = 0;
   double *scal_ = nullptr, *aux_ = nullptr, *misc_ = nullptr;
   double *K0dev_ = nullptr, *msig_ = nullptr;
+  double* msig4_ = nullptr;          // non-dyadic first step: 64 sub-element matrices
+  std::vector<double> msig4_host_;   // their host copy (outlives the upload)
   bool gs_ = cfg_.smoother == 1;  // eight-colour symmetric Gauss-Seidel instead of damped Jacobi
   int* bad_ = nullptr;
   double* hscal_ = nullptr;  // pinned: device scalars read back (main, aux)
@@ -1397,16 +1408,21 @@ Status validate(const hmg_config& c, std::vector<Grid>* grids) {
     return fail(HMG_E_INVALID, "the FP16 displacement cast needs an FP32-storage precision");
   if (c.smoother == 1 && c.nx > 1024)
     return fail(HMG_E_INVALID, "the Gauss-Seidel smoother takes at most 1024 cells along x");
+  if (c.nondyadic != 0 && c.nondyadic != 1) return fail(HMG_E_INVALID, "nondyadic must be 0 or 1");
   grids->clear();
   Grid g{c.nx, c.ny, c.nz, (int64_t)c.nx * c.ny * c.nz};
   grids->push_back(g);
   while (true) {
     if (c.levels > 0 && (int)grids->size() == c.levels) break;
     const Grid& f = grids->back();
-    if (f.nx % 2 || f.ny % 2 || f.nz % 2 || f.nx / 2 < 4 || f.ny / 2 < 4 || f.nz / 2 < 4) break;
-    Grid h{f.nx / 2, f.ny / 2, f.nz / 2, (int64_t)(f.nx / 2) * (f.ny / 2) * (f.nz / 2)};
+    // the first step divides by 4 with non-dyadic coarsening (Sec. 4.2)
+    const int F = (c.nondyadic && grids->size() == 1) ? 4 : 2;
+    if (f.nx % F || f.ny % F || f.nz % F || f.nx / F < 4 || f.ny / F < 4 || f.nz / F < 4) break;
+    Grid h{f.nx / F, f.ny / F, f.nz / F, (int64_t)(f.nx / F) * (f.ny / F) * (f.nz / F)};
     grids->push_back(h);
   }
+  if (c.nondyadic && grids->size() < 2)
+    return fail(HMG_E_INVALID, "non-dyadic coarsening needs every axis divisible by 4, >= 16");
   if (c.levels > 0 && (int)grids->size() != c.levels)
     return fail(HMG_E_INVALID, "cannot build %d levels on a %dx%dx%d cell", c.levels, c.nx, c.ny,
                 c.nz);
@@ -1764,8 +1780,8 @@ hmg_status hmg_batch_create(const hmg_config* base, int32_t ncells, const int32_
   Status s;
   for (int c = 0; c < ncells && s.code == HMG_OK; ++c) {
     hmg_config cfg = *base;
-    if (cfg.smoother != 0) {
-      s = fail(HMG_E_INVALID, "batched solves smooth with damped block Jacobi (smoother 0)");
+    if (cfg.smoother != 0 || cfg.nondyadic != 0 || cfg.post_fp16 != 0) {
+      s = fail(HMG_E_INVALID, "batched solves take the plain configuration (Jacobi, dyadic)");
       break;
     }
     cfg.nx = dims[3 * c];

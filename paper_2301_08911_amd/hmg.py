@@ -74,7 +74,7 @@ class Context:
 
     def __init__(self, shape, *, E0=1.0, nu=0.3, penal=3.0, Emin=1e-9, levels=0, omega=0.0,
                  precision="fp32", replace_every=None, smoother="jacobi", post_fp16=False,
-                 stream: torch.cuda.Stream | None = None):
+                 nondyadic=False, stream: torch.cuda.Stream | None = None):
         self.lib = _lib.load()
         nx, ny, nz = (int(v) for v in shape)
         self.shape = (nx, ny, nz)
@@ -87,7 +87,7 @@ class Context:
             replace_every = 20 if precision.startswith("mixed") else 0
         cfg = _lib.HmgConfig(nx, ny, nz, E0, nu, penal, Emin, levels, omega, 1, 1,
                              PRECISIONS[precision], replace_every, SMOOTHERS[smoother],
-                             int(bool(post_fp16)))
+                             int(bool(post_fp16)), int(bool(nondyadic)))
         self.config = cfg
         handle = ctypes.c_void_p()
         st = self.lib.hmg_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
