@@ -110,6 +110,23 @@ hmg_status hmg_conv3d_backward_weight(void* hip_stream, const float* x, const fl
 int64_t hmg_conv3d_workspace(int32_t B, int32_t Cin, int32_t Cout, int32_t D, int32_t H,
                              int32_t W);
 
+/* ---- allocation-free weight gradient -------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as hmg_conv3d_backward_weight (same kernels, same summation order),
+ * with the partial sums held in a fixed 32 MiB array of the library on each
+ * GPU instead of a workspace argument.  Calls no allocating routine.
+ * Limit: hmg_conv3d_workspace(B, Cin, Cout, D, H, W) must not exceed
+ * hmg_conv3d_noalloc_scratch_floats() (Cin * Cout <= 4854), else
+ * HMG_E_INVALID.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (other streams or host threads) race and must be
+ * serialized by the caller.  dw and dbias accumulate as in the workspace form.
+ * HMG_E_DEVICE if the array's device address cannot be looked up. */
+hmg_status hmg_conv3d_backward_weight_noalloc(void* hip_stream, const float* x, const float* dz,
+                                              float* dw, float* dbias, int32_t B, int32_t Cin,
+                                              int32_t Cout, int32_t D, int32_t H, int32_t W);
+int64_t hmg_conv3d_noalloc_scratch_floats(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,8 @@ SYMBOLS = (
     "hmg_nn_set_params", "hmg_nn_get_grads", "hmg_nn_forward", "hmg_nn_backward",
     "hmg_nn_zero_grad", "hmg_nn_adam_step", "hmg_nn_mse", "hmg_warm_start",
     "hmg_conv3d_forward", "hmg_conv3d_backward_data", "hmg_conv3d_backward_weight",
-    "hmg_conv3d_workspace",
+    "hmg_conv3d_workspace", "hmg_conv3d_backward_weight_noalloc",
+    "hmg_conv3d_noalloc_scratch_floats",
 )
 
 
@@ -108,6 +109,9 @@ def load() -> ctypes.CDLL:
         "hmg_conv3d_backward_weight": ([vp, vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32],
                                        i32),
         "hmg_conv3d_workspace": ([i32, i32, i32, i32, i32, i32], i64),
+        "hmg_conv3d_backward_weight_noalloc": ([vp, vp, vp, vp, vp, i32, i32, i32, i32, i32, i32],
+                                               i32),
+        "hmg_conv3d_noalloc_scratch_floats": ([], i64),
     }
     for name, (args, ret) in sig.items():
         fn = getattr(lib, name)

@@ -163,3 +163,17 @@ def conv3d_backward_weight(x, dz, dw, dbias, stream=None):
                                           _ptr(_f32(dw, "dw")), _ptr(dbias), _ptr(work),
                                           B, Cin, Cout, D, H, W), "hmg_conv3d_backward_weight")
     return dw, dbias
+
+
+def conv3d_backward_weight_noalloc(x, dz, dw, dbias, stream=None):
+    """hmg_conv3d_backward_weight_noalloc: the same gradient with the library's
+    fixed device scratch instead of a workspace (nothing is allocated)."""
+    lib = _lib.load()
+    B, Cin, D, H, W = _dims(_f32(x, "x"))
+    Cout = dz.shape[1]
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib.hmg_conv3d_backward_weight_noalloc(ctypes.c_void_p(s), _ptr(x), _ptr(_f32(dz, "dz")),
+                                                  _ptr(_f32(dw, "dw")), _ptr(dbias),
+                                                  B, Cin, Cout, D, H, W),
+           "hmg_conv3d_backward_weight_noalloc")
+    return dw, dbias
