@@ -276,7 +276,9 @@ typedef enum {
   HMG_K_POST_SMOOTH = 2,   /* z = z1 + D^-1 ((r - m) - K z1), z1 = z0 + P e            */
   HMG_K_UPDATE = 3,        /* x += alpha p (FP64), r -= alpha q                          */
   HMG_K_TRUE_RESIDUAL = 4, /* r = f - K x in FP64                                        */
-  HMG_K_JACOBI = 5         /* z0 = D^-1 (r - m), level 0, all cases per vertex           */
+  HMG_K_JACOBI = 5,        /* z0 = D^-1 (r - m), level 0, all cases per vertex           */
+  HMG_K_GS_FORWARD = 6,    /* level-0 Gauss-Seidel sweep 0..7 from zero (4 launches)     */
+  HMG_K_GS_BACKWARD = 7    /* level-0 Gauss-Seidel sweep 7..0 with (r - m).z (4 launches) */
 } hmg_kernel;
 
 /* enable != 0 clears the counters and starts recording a HIP event pair around

@@ -29,6 +29,8 @@
 // pair k, rows of pairs > k and the old values of its own rows.  It skips
 // their loads, so the first sweep needs no cleared buffer.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "hmg_internal.hpp"
 
@@ -36,8 +38,7 @@ namespace hmg {
 namespace {
 
 constexpr int GS_THREADS = 256;
-constexpr int GS_ITEMS0 = 1024;  // vertex pairs held in LDS per step, level 0 (one case)
-constexpr int GS_ITEMSC = 256;   // coarse levels (six cases per item)
+constexpr int GS_ITEMSC = 256;   // vertex pairs per LDS step (one per thread, six cases each)
 
 template <typename T>
 __device__ __forceinline__ double to_d(T v) {
@@ -76,6 +77,16 @@ __device__ __forceinline__ void block_apply(const A (&D)[6], A r0, A r1, A r2, A
   o[2] = D[5] * r0 + D[4] * r1 + D[2] * r2;
 }
 
+template <class F, int... I>
+__device__ __forceinline__ void static_for27_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, d>) for d = 0..26 in order.
+template <class F>
+__device__ __forceinline__ void static_for27(F& f) {
+  static_for27_impl(f, std::make_integer_sequence<int, 27>{});
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
@@ -93,6 +104,20 @@ __device__ __forceinline__ double block_total(double v, double* lds) {
   return s;
 }
 
+// Block (blockIdx.x, blockIdx.y) -> (row block bx, load case c).  Workgroups go
+// to the 8 XCDs round robin; consecutive logical blocks are gathered on one
+// XCD, so the row blocks of neighbouring z-planes, which read each other's
+// neighbour rows, share that XCD's L2.
+__device__ __forceinline__ void xcd_block(int& c, int& bx) {
+  const int nbx = gridDim.x;
+  const int tot = nbx * gridDim.y;
+  const int lin = blockIdx.x + nbx * blockIdx.y;
+  const int q = tot >> 3, rem = tot & 7, xcd = lin & 7;
+  const int logical = xcd * q + (xcd < rem ? xcd : rem) + (lin >> 3);
+  c = logical / nbx;
+  bx = logical - c * nbx;
+}
+
 // ------------------------------------------------------------------ level 0
 // The ten distinct magnitudes of K0 (see k0_sel); every loop below that
 // touches K0 is unrolled, so each entry is one of these kernel-argument
@@ -108,204 +133,107 @@ __device__ __forceinline__ T k0e(const K0Vals<T>& kv, int a, int i, int b, int j
   return (sel & 1) ? -kv.v[sel >> 1] : kv.v[sel >> 1];
 }
 
-// New value z_v + S_v^-1 ((r - m)_v - [K z]_v) at one vertex.  `plane(p, pl)`
-// fills pl[(dx + 1) + 3 (dy + 1)][k] with z at offset (dx, dy, p - 1).  The
-// incident element e = e0 + 2 e1 + 4 e2 has its origin at
-// v + (e0 - 1, e1 - 1, e2 - 1), holds v as local node 7 - e and its node b at
-// offset (e0 + b0 - 1, e1 + b1 - 1, e2 + b2 - 1); sv[e] is its scale.  The
-// three neighbour planes are visited in turn, so only one is live.
-template <typename T, class Plane>
-__device__ __forceinline__ void gs0_vertex(const K0Vals<T>& kv, const T (&sv)[8], Plane&& plane,
-                                           T r0, T r1, T r2, T (&out)[3]) {
-  T w[8][3];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) w[e][0] = w[e][1] = w[e][2] = T(0);
-  T centre[3];
-#pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    T pl[9][3];
-    plane(p, pl);
-    if (p == 1)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) centre[k] = pl[4][k];
+// ------------------------------------------------------- six cases per thread
+// Stencil sources of the generic pair kernel below.  block<d>() gives the 3x3
+// coefficient block of row v towards neighbour v + d (d = dx + 3 dy + 9 dz
+// with offsets in 0..2), inv() the inverse of the diagonal block S_v.
+
+// Level 0, matrix free (Eq. st-assemb): the block towards offset d collects
+// s_e K0[7 - e, b] over the incident elements e that hold v + d as their node
+// b (1, 2, 4 or 8 of them); it is formed once and applied to all six cases.
+template <typename T>
+struct SrcLevel0 {
+  static constexpr bool kDiff = false;
+  K0Vals<T> kv;
+  const T* __restrict__ s;
+  Grid g;
+  struct Loc {
+    T sv[8];
+  };
+  __device__ __forceinline__ void load(int x, int y, int zz, int64_t, Loc& L) const {
+    const int xm = x == 0 ? g.nx - 1 : x - 1;
+    const int ym = wrap(y - 1, g.ny), zm = wrap(zz - 1, g.nz);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int a = 7 - e, e0 = e & 1, e1 = (e >> 1) & 1, b2 = p - (e >> 2);
-      if (b2 < 0 || b2 > 1) continue;
-#pragma unroll
-      for (int b01 = 0; b01 < 4; ++b01) {
-        const int b = b01 + 4 * b2;
-        const T* u = pl[(e0 + (b01 & 1)) + 3 * (e1 + (b01 >> 1))];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-          w[e][i] += k0e(kv, a, i, b, 0) * u[0] + k0e(kv, a, i, b, 1) * u[1] +
-                     k0e(kv, a, i, b, 2) * u[2];
-      }
+      const int ex = (e & 1) ? x : xm, ey = ((e >> 1) & 1) ? y : ym, ez = (e >> 2) ? zz : zm;
+      L.sv[e] = s[ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez)];
     }
   }
-  T y[3] = {T(0), T(0), T(0)};
-  T S[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  template <int D>
+  __device__ __forceinline__ void block(const Loc& L, T (&K)[9]) const {
+    constexpr int d0 = D % 3, d1 = (D / 3) % 3, d2 = D / 9;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int a = 7 - e;
+    for (int t = 0; t < 9; ++t) K[t] = T(0);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) y[i] += sv[e] * w[e][i];
-    S[0] += sv[e] * k0e(kv, a, 0, a, 0);
-    S[1] += sv[e] * k0e(kv, a, 1, a, 1);
-    S[2] += sv[e] * k0e(kv, a, 2, a, 2);
-    S[3] += sv[e] * k0e(kv, a, 0, a, 1);
-    S[4] += sv[e] * k0e(kv, a, 1, a, 2);
-    S[5] += sv[e] * k0e(kv, a, 0, a, 2);
+    for (int e = 0; e < 8; ++e) {
+      const int b0 = d0 - (e & 1), b1 = d1 - ((e >> 1) & 1), b2 = d2 - (e >> 2);
+      if (b0 < 0 || b0 > 1 || b1 < 0 || b1 > 1 || b2 < 0 || b2 > 1) continue;
+      const int a = 7 - e, b = b0 + 2 * b1 + 4 * b2;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) K[i * 3 + j] += L.sv[e] * k0e(kv, a, i, b, j);
+    }
   }
-  T D[6];
-  sym3_inverse(S, D);
-  T dz[3];
-  block_apply(D, r0 - y[0], r1 - y[1], r2 - y[2], dz);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) out[k] = centre[k] + dz[k];
-}
+  __device__ __forceinline__ void inv(const Loc&, const T (&Kc)[9], int64_t, T (&D)[6]) const {
+    const T S[6] = {Kc[0], Kc[4], Kc[8], Kc[1], Kc[5], Kc[2]};
+    sym3_inverse(S, D);
+  }
+};
 
-// Pair k of one load case (blockIdx.y) on rows [blockIdx.x * rpb, ... + rpb).
-// first: x parity relaxed first (0 in a forward sweep, 1 in a backward one).
-// s the element scales, r the level's right-hand side, mean its per-component
-// means (S_MEAN* slots, or null), z relaxed in place, q optional, scal the
-// active cases (or null).  With dot set, the block partials of (r - m).z
-// (S_RZNEW) and q.z (S_QZ) over the vertices it finishes go to column
-// k * gridDim.x + blockIdx.x.
-template <typename T>
-__global__ void __launch_bounds__(GS_THREADS)
-gs0_pair_kernel(Grid g, K0Vals<T> kv, const T* __restrict__ s, const T* __restrict__ r,
-                const double* __restrict__ mean, T* __restrict__ z, const T* __restrict__ q,
-                const double* __restrict__ scal, Partials part, int dot, int k, int first,
-                int fresh, int rpb) {
-  __shared__ T nw[GS_ITEMS0][3];
-  __shared__ double red[GS_THREADS / 64];
-  const int c = blockIdx.y;
-  const int np = g.nx >> 1, hy = g.ny >> 1;
-  const int rows = hy * (g.nz >> 1);
-  const int rs = max(1, GS_ITEMS0 / np);
-  const int rb0 = blockIdx.x * rpb, rb1 = min(rows, rb0 + rpb);
-  const int64_t n = g.n;
-  const bool on = case_on(scal, c);
-  double acc_rz = 0.0, acc_qz = 0.0;
-  if (on) {
-    double m[3] = {0.0, 0.0, 0.0};
-    if (mean)
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) m[kk] = mean[(S_MEAN0 + kk) * 8 + c];
-    T* zc[3];
-    const T* rc[3];
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk) {
-      zc[kk] = z + (int64_t)(c * 3 + kk) * n;
-      rc[kk] = r + (int64_t)(c * 3 + kk) * n;
-    }
-    const int py = k & 1, pz = k >> 1;
-    for (int rb = rb0; rb < rb1; rb += rs) {
-      const int nitems = min(rs, rb1 - rb) * np;
-#pragma unroll 1
-      for (int step = 0; step < 2; ++step) {
-        const int xpar = step == 0 ? first : 1 - first;
-#pragma unroll 1
-        for (int w = threadIdx.x; w < nitems; w += GS_THREADS) {
-          const int j = rb + w / np, px = w % np;
-          const int y = 2 * (j % hy) + py, zz = 2 * (j / hy) + pz;
-          const int x = 2 * px + xpar;
-          const int xs[3] = {x == 0 ? g.nx - 1 : x - 1, x, x + 1 == g.nx ? 0 : x + 1};
-          // LDS items of the own-row neighbours (x - 1, x + 1) in the second step
-          const int wl = w - px + (first == 0 ? px : (px == 0 ? np - 1 : px - 1));
-          const int wr = w - px + (first == 0 ? (px + 1 == np ? 0 : px + 1) : px);
-          auto plane = [&](int p, T(&pl)[9][3]) {
-            const int dz = p - 1;
-            const int zq = wrap(zz + dz, g.nz);
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-              const int yy = wrap(y + dy, g.ny);
-              const int64_t rbase = (int64_t)g.nx * (yy + (int64_t)g.ny * zq);
-              const bool own = dy == 0 && dz == 0;
-              const bool zero = fresh && (own || row_pair(k, dy, dz) > k);
-#pragma unroll
-              for (int dx = 0; dx < 3; ++dx) {
-                T* o = pl[dx + 3 * (dy + 1)];
-                if (own && dx != 1 && step == 1) {
-                  const int wi = dx == 0 ? wl : wr;
-#pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) o[kk] = nw[wi][kk];
-                } else if (zero) {
-#pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) o[kk] = T(0);
-                } else {
-#pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) o[kk] = zc[kk][rbase + xs[dx]];
-                }
-              }
-            }
-          };
-          T sv[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int ex = (e & 1) ? x : xs[0];
-            const int ey = ((e >> 1) & 1) ? y : wrap(y - 1, g.ny);
-            const int ez = (e >> 2) ? zz : wrap(zz - 1, g.nz);
-            sv[e] = s[ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez)];
-          }
-          const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * zz);
-          const T r0 = (T)((double)rc[0][v] - m[0]);
-          const T r1 = (T)((double)rc[1][v] - m[1]);
-          const T r2 = (T)((double)rc[2][v] - m[2]);
-          T out[3];
-          gs0_vertex<T>(kv, sv, plane, r0, r1, r2, out);
-#pragma unroll
-          for (int kk = 0; kk < 3; ++kk) zc[kk][v] = out[kk];
-          if (step == 0)
-#pragma unroll
-            for (int kk = 0; kk < 3; ++kk) nw[w][kk] = out[kk];
-          if (dot) {
-            acc_rz += (double)r0 * (double)out[0] + (double)r1 * (double)out[1] +
-                      (double)r2 * (double)out[2];
-            if (q)
-#pragma unroll
-              for (int kk = 0; kk < 3; ++kk)
-                acc_qz += (double)q[(int64_t)(c * 3 + kk) * n + v] * (double)out[kk];
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-  if (dot) {
-    const int col = k * gridDim.x + blockIdx.x;
-    const double t0 = block_total(acc_rz, red);
-    if (threadIdx.x == 0) part.buf[(int64_t)(S_RZNEW * 8 + c) * part.stride + col] = t0;
-    if (q) {
-      const double t1 = block_total(acc_qz, red);
-      if (threadIdx.x == 0) part.buf[(int64_t)(S_QZ * 8 + c) * part.stride + col] = t1;
-    }
-  }
-}
-
-// ------------------------------------------------------------- coarse levels
-// Stored stencils st[((d*3 + p)*3 + q) * n + v] and block inverses
-// dinv[t * n + v], t = (xx, yy, zz, xy, yz, xz) of S_v^-1 (undamped).  Rounded
+// Coarse levels: stored stencils st[((d*3 + p)*3 + q) * n + v] and block
+// inverses dinv[t * n + v], t = (xx, yy, zz, xy, yz, xz) of S_v^-1.  Rounded
 // (bf16) stencils use the centre block implied by the row sum and apply the
 // operator in difference form, as the other coarse kernels do.
-template <typename V, typename W>
+template <typename W>
+struct SrcStored {
+  static constexpr bool kDiff = std::is_same<W, bf16>::value;
+  const W* __restrict__ st;
+  const W* __restrict__ dinv;
+  int64_t n;
+  struct Loc {
+    int64_t v;
+  };
+  __device__ __forceinline__ void load(int, int, int, int64_t v, Loc& L) const { L.v = v; }
+  template <int D, typename A>
+  __device__ __forceinline__ void block(const Loc& L, A (&K)[9]) const {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) K[t] = (A)st[(int64_t)(D * 9 + t) * n + L.v];
+  }
+  template <typename A>
+  __device__ __forceinline__ void inv(const Loc& L, const A (&)[9], int64_t, A (&D)[6]) const {
+#pragma unroll
+    for (int t = 0; t < 6; ++t) D[t] = (A)dinv[(int64_t)t * n + L.v];
+  }
+};
+
+// One colour pair (rows of pair k) of all six load cases: a thread per vertex
+// pair, the first x parity, an LDS barrier, then the second.  With `dot`, the
+// block partials of (r - m).z (S_RZNEW) and q.z (S_QZ) of the finished rows
+// go to column k * gridDim.x + bx of `part`.
+template <typename V, class Src>
 __global__ void __launch_bounds__(GS_THREADS)
-gsc_pair_kernel(Grid g, const W* __restrict__ st, const W* __restrict__ dinv,
-                const V* __restrict__ r, const double* __restrict__ mean, V* z,
-                const double* __restrict__ scal, int k, int first, int fresh, int rpb) {
+gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restrict__ mean,
+               V* __restrict__ z, const V* __restrict__ q, const double* __restrict__ scal,
+               Partials part, int dot, int k, int first, int fresh, int rpb) {
   using A = typename Acc<V>::type;
-  constexpr bool kDiff = std::is_same<W, bf16>::value;
+  constexpr bool kDiff = Src::kDiff;
   __shared__ A nw[GS_ITEMSC][NCASE][3];
+  __shared__ double red[GS_THREADS / 64];
   bool on[NCASE];
 #pragma unroll
   for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
   const int np = g.nx >> 1, hy = g.ny >> 1;
   const int rows = hy * (g.nz >> 1);
   const int rs = max(1, GS_ITEMSC / np);
-  const int rb0 = blockIdx.x * rpb, rb1 = min(rows, rb0 + rpb);
-  const int n = (int)g.n;
+  int c0, bx;
+  xcd_block(c0, bx);
+  const int rb0 = bx * rpb, rb1 = min(rows, rb0 + rpb);
+  const int64_t n = g.n;
   const int py = k & 1, pz = k >> 1;
+  double acc_rz[NCASE], acc_qz[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) acc_rz[c] = acc_qz[c] = 0.0;
   for (int rb = rb0; rb < rb1; rb += rs) {
     const int nitems = min(rs, rb1 - rb) * np;
 #pragma unroll 1
@@ -316,10 +244,13 @@ gsc_pair_kernel(Grid g, const W* __restrict__ st, const W* __restrict__ dinv,
         const int j = rb + w / np, px = w % np;
         const int y = 2 * (j % hy) + py, zz = 2 * (j / hy) + pz;
         const int x = 2 * px + xpar;
-        const int v = x + g.nx * (y + g.ny * zz);
+        const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * zz);
         const int xs[3] = {x == 0 ? g.nx - 1 : x - 1, x, x + 1 == g.nx ? 0 : x + 1};
+        // LDS items of the own-row neighbours (x - 1, x + 1) in the second step
         const int wl = w - px + (first == 0 ? px : (px == 0 ? np - 1 : px - 1));
         const int wr = w - px + (first == 0 ? (px + 1 == np ? 0 : px + 1) : px);
+        typename Src::Loc loc;
+        src.load(x, y, zz, v, loc);
         A uc[NCASE][3];
 #pragma unroll
         for (int c = 0; c < NCASE; ++c)
@@ -329,59 +260,61 @@ gsc_pair_kernel(Grid g, const W* __restrict__ st, const W* __restrict__ dinv,
         A acc[NCASE][3];
 #pragma unroll
         for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
-        for (int dz = -1; dz <= 1; ++dz)
-          for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = wrap(y + dy, g.ny), zq = wrap(zz + dz, g.nz);
-            const int rbase = g.nx * (yy + g.ny * zq);
-            const bool own = dy == 0 && dz == 0;
-            const bool zero = fresh && (own || row_pair(k, dy, dz) > k);
+        A Kc[9];
+        // the 27 offsets; d is a compile-time constant in every iteration
+        auto visit = [&](auto dconst) {
+          constexpr int d = decltype(dconst)::value;
+          constexpr int dx = d % 3, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+          constexpr bool own = dy == 0 && dz == 0;
+          if (kDiff && d == 13) return;
+          const bool from_lds = own && dx != 1 && step == 1;
+          const bool zero = fresh && (own || row_pair(k, dy, dz) > k);
+          A K[9];
+          src.template block<d>(loc, K);
+          if (d == 13)
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              const int d = dx + 3 * (dy + 1) + 9 * (dz + 1);
-              if (kDiff && d == 13) continue;
-              const bool from_lds = own && dx != 1 && step == 1;
-              if (zero && !from_lds && !(own && dx == 1 && !kDiff)) continue;
-              A K[9];
+            for (int t = 0; t < 9; ++t) Kc[t] = K[t];
+          if (zero && !from_lds && !(own && dx == 1)) return;
+          const int64_t rbase =
+              (int64_t)g.nx * (wrap(y + dy, g.ny) + (int64_t)g.ny * wrap(zz + dz, g.nz));
 #pragma unroll
-              for (int t = 0; t < 9; ++t) K[t] = (A)st[(int64_t)(d * 9 + t) * n + v];
+          for (int c = 0; c < NCASE; ++c) {
+            A u[3];
+            if (from_lds) {
+              const int wi = dx == 0 ? wl : wr;
 #pragma unroll
-              for (int c = 0; c < NCASE; ++c) {
-                A u[3];
-                if (from_lds) {
-                  const int wi = dx == 0 ? wl : wr;
+              for (int kk = 0; kk < 3; ++kk) u[kk] = nw[wi][c][kk];
+            } else if (own && dx == 1) {
 #pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) u[kk] = nw[wi][c][kk];
-                } else if (own && dx == 1) {
+              for (int kk = 0; kk < 3; ++kk) u[kk] = uc[c][kk];
+            } else if (zero) {
 #pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) u[kk] = uc[c][kk];
-                } else if (zero) {
+              for (int kk = 0; kk < 3; ++kk) u[kk] = A(0);
+            } else {
 #pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) u[kk] = A(0);
-                } else {
-#pragma unroll
-                  for (int kk = 0; kk < 3; ++kk)
-                    u[kk] = (A)z[(int64_t)(c * 3 + kk) * n + rbase + xs[dx]];
-                }
-                if (kDiff)
-#pragma unroll
-                  for (int kk = 0; kk < 3; ++kk) u[kk] -= uc[c][kk];
-                acc[c][0] += K[0] * u[0] + K[1] * u[1] + K[2] * u[2];
-                acc[c][1] += K[3] * u[0] + K[4] * u[1] + K[5] * u[2];
-                acc[c][2] += K[6] * u[0] + K[7] * u[1] + K[8] * u[2];
-              }
+              for (int kk = 0; kk < 3; ++kk)
+                u[kk] = (A)z[(int64_t)(c * 3 + kk) * n + rbase + xs[dx]];
             }
-          }
-        A D[6];
+            if (kDiff)
 #pragma unroll
-        for (int t = 0; t < 6; ++t) D[t] = (A)dinv[(int64_t)t * n + v];
+              for (int kk = 0; kk < 3; ++kk) u[kk] -= uc[c][kk];
+            acc[c][0] += K[0] * u[0] + K[1] * u[1] + K[2] * u[2];
+            acc[c][1] += K[3] * u[0] + K[4] * u[1] + K[5] * u[2];
+            acc[c][2] += K[6] * u[0] + K[7] * u[1] + K[8] * u[2];
+          }
+        };
+        static_for27(visit);
+        A D[6];
+        src.inv(loc, Kc, v, D);
 #pragma unroll
         for (int c = 0; c < NCASE; ++c) {
-          A res[3];
+          A rv[3], res[3];
 #pragma unroll
-          for (int kk = 0; kk < 3; ++kk)
-            res[kk] = (A)(to_d(r[(int64_t)(c * 3 + kk) * n + v]) -
-                          (mean ? mean[(S_MEAN0 + kk) * 8 + c] : 0.0)) -
-                      acc[c][kk];
+          for (int kk = 0; kk < 3; ++kk) {
+            rv[kk] = (A)(to_d(r[(int64_t)(c * 3 + kk) * n + v]) -
+                         (mean ? mean[(S_MEAN0 + kk) * 8 + c] : 0.0));
+            res[kk] = rv[kk] - acc[c][kk];
+          }
           A dzv[3];
           block_apply(D, res[0], res[1], res[2], dzv);
 #pragma unroll
@@ -389,17 +322,33 @@ gsc_pair_kernel(Grid g, const W* __restrict__ st, const W* __restrict__ dinv,
             const V nv = (V)(uc[c][kk] + dzv[kk]);
             if (on[c]) z[(int64_t)(c * 3 + kk) * n + v] = nv;
             if (step == 0) nw[w][c][kk] = (A)nv;
+            if (dot) {
+              acc_rz[c] += (double)rv[kk] * (double)(A)nv;
+              if (q) acc_qz[c] += (double)(A)q[(int64_t)(c * 3 + kk) * n + v] * (double)(A)nv;
+            }
           }
         }
       }
       __syncthreads();
     }
   }
+  if (dot) {
+    const int col = k * gridDim.x + bx;
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) {
+      const double t0 = block_total(acc_rz[c], red);
+      if (threadIdx.x == 0) part.buf[(int64_t)(S_RZNEW * 8 + c) * part.stride + col] = t0;
+      if (q) {
+        const double t1 = block_total(acc_qz[c], red);
+        if (threadIdx.x == 0) part.buf[(int64_t)(S_QZ * 8 + c) * part.stride + col] = t1;
+      }
+    }
+  }
 }
 
 int gs_rows(const Grid& g) { return (g.ny / 2) * (g.nz / 2); }
 
-// Rows per block: whole LDS steps, at most `cap` blocks per case.
+// Rows per block: whole LDS steps, at most `cap` blocks.
 int gs_rows_per_block(const Grid& g, int items, int cap) {
   const int np = g.nx / 2;
   const int rs = std::max(1, items / np);
@@ -408,14 +357,16 @@ int gs_rows_per_block(const Grid& g, int items, int cap) {
   return rs * steps;
 }
 
+constexpr int GS_BLOCK_CAP = 4096;
+
 }  // namespace
 
 bool gs_supported(const Grid& g) {
-  return g.nx % 2 == 0 && g.ny % 2 == 0 && g.nz % 2 == 0 && g.nx / 2 <= GS_ITEMS0 && g.nx >= 2;
+  return g.nx % 2 == 0 && g.ny % 2 == 0 && g.nz % 2 == 0 && g.nx / 2 <= GS_ITEMSC && g.nx >= 2;
 }
 
 int gs0_blocks_per_case(const Grid& g) {
-  const int rpb = gs_rows_per_block(g, GS_ITEMS0, 1024);
+  const int rpb = gs_rows_per_block(g, GS_ITEMSC, GS_BLOCK_CAP);
   return (gs_rows(g) + rpb - 1) / rpb;
 }
 
@@ -423,14 +374,16 @@ template <typename T>
 void gs0_sweep(const Grid& g, const double* k0v, const T* s, const T* r, const double* mean, T* z,
                const T* q, const double* scal, Partials part, bool forward, bool fresh,
                int* nblk_out, hipStream_t st) {
-  K0Vals<T> kv;
-  for (int i = 0; i < 10; ++i) kv.v[i] = (T)k0v[i];
-  const int rpb = gs_rows_per_block(g, GS_ITEMS0, 1024);
+  SrcLevel0<T> src;
+  for (int i = 0; i < 10; ++i) src.kv.v[i] = (T)k0v[i];
+  src.s = s;
+  src.g = g;
+  const int rpb = gs_rows_per_block(g, GS_ITEMSC, GS_BLOCK_CAP);
   const int nblk = (gs_rows(g) + rpb - 1) / rpb;
   for (int i = 0; i < 4; ++i) {
     const int k = forward ? i : 3 - i;
-    hipLaunchKernelGGL(gs0_pair_kernel<T>, dim3(nblk, NCASE), dim3(GS_THREADS), 0, st, g, kv, s, r,
-                       mean, z, q, scal, part, nblk_out ? 1 : 0, k, forward ? 0 : 1,
+    hipLaunchKernelGGL((gs_pair_kernel<T, SrcLevel0<T>>), dim3(nblk), dim3(GS_THREADS), 0, st, g,
+                       src, r, mean, z, q, scal, part, nblk_out ? 1 : 0, k, forward ? 0 : 1,
                        (forward && fresh) ? 1 : 0, rpb);
   }
   if (nblk_out) *nblk_out = 4 * nblk;
@@ -439,12 +392,14 @@ void gs0_sweep(const Grid& g, const double* k0v, const T* s, const T* r, const d
 template <typename V, typename W>
 void gsc_sweep(const Grid& g, const W* stc, const W* dinv, const V* r, const double* mean, V* z,
                const double* scal, bool forward, bool fresh, hipStream_t st) {
-  const int rpb = gs_rows_per_block(g, GS_ITEMSC, 2048);
+  const SrcStored<W> src{stc, dinv, g.n};
+  const int rpb = gs_rows_per_block(g, GS_ITEMSC, GS_BLOCK_CAP);
   const int nblk = (gs_rows(g) + rpb - 1) / rpb;
   for (int i = 0; i < 4; ++i) {
     const int k = forward ? i : 3 - i;
-    hipLaunchKernelGGL((gsc_pair_kernel<V, W>), dim3(nblk), dim3(GS_THREADS), 0, st, g, stc, dinv,
-                       r, mean, z, scal, k, forward ? 0 : 1, (forward && fresh) ? 1 : 0, rpb);
+    hipLaunchKernelGGL((gs_pair_kernel<V, SrcStored<W>>), dim3(nblk), dim3(GS_THREADS), 0, st, g,
+                       src, r, mean, z, (const V*)nullptr, scal, Partials{}, 0, k,
+                       forward ? 0 : 1, (forward && fresh) ? 1 : 0, rpb);
   }
 }
 

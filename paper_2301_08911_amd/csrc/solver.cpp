@@ -60,7 +60,7 @@ class DeviceArena {
 // around the tracked launches; elapsed times are harvested when read.
 class KernelClock {
  public:
-  static constexpr int NK = 6;
+  static constexpr int NK = 8;
   ~KernelClock() {
     for (auto& p : pending_) {
       (void)hipEventDestroy(p.a);
@@ -843,15 +843,23 @@ class Solver final : public SolverIface {
     if (gs_) {
       // forward sweep from zero, residual + restriction, coarse correction,
       // backward sweep with the partial dot products of the result
-      gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, nullptr, scal, part_, true, true, nullptr, st_);
-      op0_residual<T, V>(L0, r0, zout, t_, scal);
+      // Algorithmic bytes of a sweep per vertex and active case: r read, z
+      // written, and (backward) z read once; plus s per vertex.
+      clock.timed(HMG_K_GS_FORWARD, vn * (nact * 6 * TB + TB), st_, [&] {
+        gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, nullptr, scal, part_, true, true, nullptr,
+                     st_);
+      });
+      clock.timed(HMG_K_RESIDUAL, vn * (nact * 3 * (2 * TB + VB) + TB), st_,
+                  [&] { op0_residual<T, V>(L0, r0, zout, t_, scal); });
       restrict_to<V>(g0, grids_[1], t_, lev_[1].r, scal, st_);
       descend(1, scal);
       if (L == 2)
         prolong_add<T, T>(g0, grids_[1], zout, zc_, scal, false, st_);
       else
         prolong_add<T, V>(g0, grids_[1], zout, lev_[1].z, scal, false, st_);
-      gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, qpr, scal, part_, false, false, nb, st_);
+      clock.timed(HMG_K_GS_BACKWARD, vn * (nact * 3 * (3 * TB + (qpr ? TB : 0)) + TB), st_, [&] {
+        gs0_sweep<T>(g0, ec_.kv, s_, r0, scal, zout, qpr, scal, part_, false, false, nb, st_);
+      });
       return check_hip("vcycle");
     }
     clock.timed(HMG_K_JACOBI, vn * (nact * 6 * TB + 6 * TB), st_,
