@@ -190,7 +190,9 @@ hmg_status hmg_oc_update(hmg_ctx ctx, float* x_dev, const float* dfdx_dev, doubl
 hmg_status hmg_filter(hmg_ctx ctx, const float* in_dev, float* out_dev, double radius,
                       int32_t adjoint);
 
-/* Copy the last solution (field type, case-major SoA, zero mean) to u_dev. */
+/* Copy the current iterate (field type, case-major SoA) to u_dev: the last
+ * solution (zero mean), or, after an accepted hmg_warm_start and before the
+ * next solve, that guess.  HMG_E_STATE if there is neither. */
 hmg_status hmg_get_displacement(hmg_ctx ctx, void* u_dev);
 
 /* ---- design-space steps of the optimization loop --------------------------- */

@@ -673,7 +673,8 @@ class Solver final : public SolverIface {
   }
 
   Status get_disp(void* u) override {
-    if (!have_solution_) return fail(HMG_E_STATE, "hmg_solve_cases has not been called");
+    if (!have_solution_ && !have_iterate_)
+      return fail(HMG_E_STATE, "neither hmg_solve_cases nor an accepted warm start has run");
     vec_convert<double, T>((T*)u, x_, (int64_t)NCASE * 3 * grids_[0].n, st_);
     return check_hip("get_displacement");
   }

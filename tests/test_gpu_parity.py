@@ -299,14 +299,23 @@ def test_deterministic_bitwise():
     assert np.array_equal(out[0][1], out[1][1])
 
 
-def test_one_level_grid_direct_solve():
+@pytest.mark.parametrize("contrast", ["mild", "voids"])
+def test_one_level_grid_direct_solve(contrast):
+    """With no coarse level the preconditioner is the exact inverse of the
+    vertex-pinned matrix followed by the mean projection, so PCG converges in
+    one iteration, for densities in [0.3, 0.9] and for the uniform[0, 0.6)
+    densities, whose s reaches 1e-9 (both measured at one iteration).  Two are
+    allowed for a last step taken when the first lands just above the
+    tolerance through the rounding of the inverse."""
     shape = (4, 4, 6)      # no coarse level: the direct solver handles level 0
-    rho = f32(I.uniform_density(shape, 17))
+    u01 = I.uniform_density(shape, 17)
+    rho = f32(0.3 + u01 if contrast == "mild" else u01)
     ctx = ctx_for(shape, "fp64")
     assert ctx.num_levels() == 1
     ctx.set_density(dev(rho))
     res = ctx.solve_cases(1e-10, 20)
-    assert res.converged and (res.iters <= 12).all(), res
+    print(contrast, "iters", res.iters.tolist(), flush=True)
+    assert res.converged and (res.iters <= 2).all(), res
     _, u, Cref = oracle_solution(rho.astype(np.float64), shape)
     assert rel(ctx.elastic_tensor(), Cref) < 1e-10
 
