@@ -275,12 +275,13 @@ const char* hmg_last_error(hmg_ctx ctx);
 typedef enum {
   HMG_K_MATVEC = 0,        /* p = z + beta p, q = K p, p.q          (level-0 operator) */
   HMG_K_RESIDUAL = 1,      /* t = (r - m) - K z0                    (level-0 operator) */
-  HMG_K_POST_SMOOTH = 2,   /* z = z1 + D^-1 ((r - m) - K z1), z1 = z0 + P e            */
+  HMG_K_POST_SMOOTH = 2,   /* z = z1 + D^-1 ((r - m) - K z1)       (level-0 operator) */
   HMG_K_UPDATE = 3,        /* x += alpha p (FP64), r -= alpha q                          */
   HMG_K_TRUE_RESIDUAL = 4, /* r = f - K x in FP64                                        */
   HMG_K_JACOBI = 5,        /* z0 = D^-1 (r - m), level 0, all cases per vertex           */
   HMG_K_GS_FORWARD = 6,    /* level-0 Gauss-Seidel sweep 0..7 from zero (4 launches)     */
-  HMG_K_GS_BACKWARD = 7    /* level-0 Gauss-Seidel sweep 7..0 with (r - m).z (4 launches) */
+  HMG_K_GS_BACKWARD = 7,   /* level-0 Gauss-Seidel sweep 7..0 with (r - m).z (4 launches) */
+  HMG_K_PROLONG = 8        /* z1 = z0 + P e, level 0 (damped-Jacobi cycle)               */
 } hmg_kernel;
 
 /* enable != 0 clears the counters and starts recording a HIP event pair around

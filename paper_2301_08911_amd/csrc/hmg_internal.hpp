@@ -145,8 +145,9 @@ void op0_apply(const Op0Launch<T>& L, const T* in, T* out, const double* scal);
 template <typename T, typename V>
 void op0_matvec_p(const Op0Launch<T>& L, const V* z, const V* pold, V* pnew, T* q,
                   const double* scal, Partials part, int* nblk_out);
-// t = (r - m) - K z0; m from scal S_MEAN* (z0 = Dinv (r - m) comes from
-// vec_jacobi0); t is stored as V (it is only restricted, never multiplied by K).
+// t = (r - m) - K z0; m from scal S_MEAN* (z0 = Dinv (r - m) from vec_jacobi0,
+// or a Gauss-Seidel sweep); t is stored as V (it is only restricted, never
+// multiplied by K).
 template <typename T, typename V>
 void op0_residual(const Op0Launch<T>& L, const T* r, const T* z0, V* t, const double* scal);
 // zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW and, if
@@ -155,8 +156,9 @@ template <typename T, typename V>
 void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
                      const T* q, const double* scal, Partials part, int* nblk_out);
 // r = f - K x evaluated in FP64 (x, s and the constants in double), stored as R.
+// tplg: the FP64 load template g[c][a][k] (LoadTpl layout) in device memory.
 template <typename R>
-void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
+void op0_force_residual(const Op0Launch<double>& L, const double* tplg, const double* x,
                         R* r, const double* scal, Partials part, int* nblk_out);
 // Upper bound of the blocks per case of any level-0 pass (FP32 or FP64 tiles).
 int op0_blocks_per_case(const Grid& g);

@@ -58,9 +58,10 @@ TileGeom tile_geom(const Grid& g, int lz_req = 0) {
   if (lz_req > 0)
     lz = lz_req < g.nz ? lz_req : g.nz;
   else
-    // about 160 blocks per CU: short z-chunks cost halo planes but keep the
-    // blocks of a wave of the grid close together (measured best at 512^3: 16)
-    while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 40960) lz = (lz + 1) / 2;
+    // about 80 blocks per CU: short z-chunks cost halo planes but keep the
+    // blocks of a wave of the grid close together (at 512^3, 32-plane chunks
+    // and 30240 blocks ran faster than 16 or 64 planes)
+    while (lz > 16 && base * ((g.nz + lz - 1) / lz) < 20480) lz = (lz + 1) / 2;
   t.lz = lz;
   t.nzc = (g.nz + lz - 1) / lz;
   t.ntiles = t.ntx * t.nty * t.nzc;
@@ -306,9 +307,11 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   // of a step are issued by distance to their use: the epilogue operands of
   // vertex plane ez and the scale of element plane ez+1 (used next step)
   // first, then vertex plane ez+3 (staged two steps later).  Every load is
-  // unconditional (planes past the chunk wrap around and go unused): a loaded
-  // register merged across a branch would make the compiler wait for all
-  // outstanding loads.
+  // unconditional (a loaded register merged across a branch would make the
+  // compiler wait for all outstanding loads), so the steps at the ends of the
+  // chunk, whose loads go unused, re-read the nearest plane of the chunk
+  // instead of the next chunk's: those re-reads hit in L2 and add no memory
+  // traffic.
   double acc0 = 0.0, acc1 = 0.0;
   T ta[4][3], tb[4][3], ga[4][3], rq[3], ucur[3], uprev[3];
   typename Op::ERaw ea, eb;
@@ -341,10 +344,12 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
     constexpr int cb = decltype(par)::value;  // row buffer read in this step
     constexpr int pb = 1 - cb;                // plane buffer receiving vertex plane ez + 1
     if (ez < z1) stage_plane(pb, ez + 1, rawn);
-    op.efetch(c, nxy * modp(ez, g.nz), exy, e_new);  // epilogue of vertex plane ez
-    s_new = ld(s, nxy * modp(ez + 1, g.nz), exy);     // scale of element plane ez+1
+    // epilogue of vertex plane ez (used for z0 <= ez < z1)
+    op.efetch(c, nxy * modp(min(max(ez, z0), z1 - 1), g.nz), exy, e_new);
+    // scale of element plane ez+1 (used for ez+1 < z1)
+    s_new = ld(s, nxy * modp(min(ez + 1, z1 - 1), g.nz), exy);
     __builtin_amdgcn_sched_barrier(0);
-    fetch_plane(ez + 3, rawn);
+    fetch_plane(min(ez + 3, z1), rawn);  // staged for ez+3 <= z1
     __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
     if (ez > z0 && ez <= z1 && outv) {
@@ -661,7 +666,29 @@ __device__ __forceinline__ void forcing_at(const Grid& g, const T* __restrict__ 
   }
 }
 
-// r = f - K x (computed in T, stored as R);  acc0 f.f, acc1 r.r
+// The same with the case's 24 template values in device memory, w[3 a + k]:
+// for a case index known only at run time (a by-value template indexed by it
+// would be copied to scratch memory).
+template <typename T>
+__device__ __forceinline__ void forcing_at(const Grid& g, const T* __restrict__ s,
+                                           const T* __restrict__ w, int gx, int gy, int gz,
+                                           T (&f)[3]) {
+  const int xm = gx == 0 ? g.nx - 1 : gx - 1;
+  const int ym = gy == 0 ? g.ny - 1 : gy - 1;
+  const int zm = gz == 0 ? g.nz - 1 : gz - 1;
+  const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+  f[0] = f[1] = f[2] = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t e = ((a & 1) ? xm : gx) + nx * ((a & 2) ? ym : gy) + nxy * ((a & 4) ? zm : gz);
+    const T se = s[e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] += se * w[3 * a + k];
+  }
+}
+
+// r = f - K x (computed in T, stored as R);  acc0 f.f, acc1 r.r.  tplg: the
+// load template g[c][a][k] in device memory.
 template <typename T, typename R>
 struct OpForceResidual {
   static constexpr int NACC = 2;
@@ -669,7 +696,7 @@ struct OpForceResidual {
   const T* x;
   R* r;
   const T* s;
-  LoadTpl<T> tpl;
+  const T* tplg;
   Grid g;
   int64_t n;
   const double* scal;
@@ -693,7 +720,7 @@ struct OpForceResidual {
   __device__ void store(int c, int64_t zoff, uint32_t xy, int gx, int gy, int gz, const T* ku,
                         const T*, const ERaw&, double& a0, double& a1) const {
     T f[3];
-    forcing_at(g, s, tpl, c, gx, gy, gz, f);
+    forcing_at(g, s, tplg + 24 * c, gx, gy, gz, f);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const T rv = f[k] - ku[k];
@@ -980,9 +1007,9 @@ void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* di
 }
 
 template <typename R>
-void op0_force_residual(const Op0Launch<double>& L, const LoadTpl<double>& tpl, const double* x,
+void op0_force_residual(const Op0Launch<double>& L, const double* tplg, const double* x,
                         R* r, const double* scal, Partials part, int* nblk_out) {
-  OpForceResidual<double, R> op{x, r, L.s, tpl, L.g, L.g.n, scal, part, S_FF, S_TRUE};
+  OpForceResidual<double, R> op{x, r, L.s, tplg, L.g, L.g.n, scal, part, S_FF, S_TRUE};
   launch_op0(L, op);
   *nblk_out = tile_geom<double>(L.g).ntiles;
 }
@@ -1023,7 +1050,7 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
                                       const T*, const double*, Partials, int*);
 #define HMG_INST1(T)                                                                             \
   template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
-  template void op0_force_residual<T>(const Op0Launch<double>&, const LoadTpl<double>&,         \
+  template void op0_force_residual<T>(const Op0Launch<double>&, const double*,                  \
                                       const double*, T*, const double*, Partials, int*);         \
   template void forcing<T>(const Grid&, const LoadTpl<double>&, const double*, T*, Partials,    \
                            int*, hipStream_t);                                                    \

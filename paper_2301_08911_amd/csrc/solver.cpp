@@ -60,7 +60,7 @@ class DeviceArena {
 // around the tracked launches; elapsed times are harvested when read.
 class KernelClock {
  public:
-  static constexpr int NK = 8;
+  static constexpr int NK = 9;
   ~KernelClock() {
     for (auto& p : pending_) {
       (void)hipEventDestroy(p.a);
@@ -266,11 +266,13 @@ class Solver final : public SolverIface {
     aux_ = (double*)A(sizeof(double) * S_NSLOT * 8);
     misc_ = (double*)A(sizeof(double) * 64);
     K0dev_ = (double*)A(sizeof(double) * 576);
+    tplg_ = (double*)A(sizeof(LoadTpl<double>));
     msig_ = (double*)A(sizeof(double) * 8 * 576);
     bad_ = (int*)A(sizeof(int) * 4);
     for (void* p : {(void*)s_, (void*)rho_, (void*)dinv0_, (void*)x_, (void*)r_, (void*)z_,
                     (void*)t_, (void*)pa_, (void*)pb_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
-                    (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)msig_,
+                    (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)tplg_,
+                    (void*)msig_,
                     (void*)bad_, (void*)s64_, (void*)rho64_})
       if (!p) return fail(HMG_E_OOM, "device allocation failed for a %dx%dx%d cell", g0.nx, g0.ny,
                           g0.nz);
@@ -282,6 +284,8 @@ class Solver final : public SolverIface {
       return fail(HMG_E_OOM, "pinned host allocation failed");
     hstage_ = hscal_ + 2 * S_NSLOT * 8;
     (void)hipMemcpyAsync(K0dev_, &ec_.K0[0][0], sizeof(double) * 576, hipMemcpyHostToDevice, st_);
+    (void)hipMemcpyAsync(tplg_, &tpl64_.g[0][0][0], sizeof(LoadTpl<double>), hipMemcpyHostToDevice,
+                         st_);
     (void)hipMemcpyAsync(msig_, &ec_.msig[0][0][0], sizeof(double) * 8 * 576, hipMemcpyHostToDevice,
                    st_);
     if (L > 1 && grids_[0].nx == 4 * grids_[1].nx) {
@@ -356,7 +360,7 @@ class Solver final : public SolverIface {
     const double eps_abs = 1e-12 * std::sqrt((double)g0.n) * (lam1 + 2 * mu1) * mean_s_;
     auto worst_relres = [&](double* out) -> Status {
       scal_set_all_active(aux_, st_);
-      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
+      op0_force_residual<T>(L64, tplg_, x_, r_, nullptr, part_, &nb);
       fin_sum(part_, S_FF, nb, aux_, true, st_);
       fin_sum(part_, S_TRUE, nb, aux_, true, st_);
       HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
@@ -379,7 +383,7 @@ class Solver final : public SolverIface {
       forcing<T>(g0, tpl64_, s64_, fbuf, part_, &nbd, st_);
       vec_dot_cases<double, T>(g0, x_, fbuf, aux_, part_, S_PQ, &nbd, st_);
       fin_sum(part_, S_PQ, nbd, aux_, true, st_);  // u.f
-      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nbd);
+      op0_force_residual<T>(L64, tplg_, x_, r_, nullptr, part_, &nbd);
       vec_dot_cases<double, T>(g0, x_, r_, aux_, part_, S_RZ, &nbd, st_);
       fin_sum(part_, S_RZ, nbd, aux_, true, st_);  // u.(f - K u)
       HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
@@ -493,7 +497,7 @@ class Solver final : public SolverIface {
       (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_FF * 8, sizeof(double) * 8,
                            hipMemcpyDeviceToDevice, st_);
     } else {
-      op0_force_residual<T>(L64, tpl64_, x_, r_, nullptr, part_, &nb);
+      op0_force_residual<T>(L64, tplg_, x_, r_, nullptr, part_, &nb);
       fin_sum(part_, S_FF, nb, scal_, true, st_);
       fin_sum(part_, S_TRUE, nb, scal_, true, st_);
       (void)hipMemcpyAsync(scal_ + S_RR * 8, scal_ + S_TRUE * 8, sizeof(double) * 8,
@@ -574,7 +578,7 @@ class Solver final : public SolverIface {
         }
         set_mask(aux_, check);
         clock.timed(HMG_K_TRUE_RESIDUAL, (double)g0.n * (count(check) * (24 + 3 * sizeof(T)) + 8),
-                    st_, [&] { op0_force_residual<T>(L64, tpl64_, x_, r_, aux_, part_, &nb); });
+                    st_, [&] { op0_force_residual<T>(L64, tplg_, x_, r_, aux_, part_, &nb); });
         fin_sum(part_, S_TRUE, nb, aux_, false, st_);
         HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
         const double* ha = hscal_ + S_NSLOT * 8;
@@ -607,7 +611,7 @@ class Solver final : public SolverIface {
     fin_mean(part_, nb, g0.n, aux_, st_);
     vec_mean_subtract<double>(g0, x_, aux_, st_);
     scal_set_all_active(aux_, st_);
-    op0_force_residual<T>(L64, tpl64_, x_, r_, aux_, part_, &nb);
+    op0_force_residual<T>(L64, tplg_, x_, r_, aux_, part_, &nb);
     fin_sum(part_, S_FF, nb, aux_, true, st_);
     fin_sum(part_, S_TRUE, nb, aux_, true, st_);
     HMG_TRY(read_scal(aux_, hscal_ + S_NSLOT * 8));
@@ -869,10 +873,13 @@ class Solver final : public SolverIface {
                 [&] { op0_residual<T, V>(L0, r0, w0_, t_, scal); });
     restrict_to<V>(g0, grids_[1], t_, lev_[1].r, scal, st_);
     descend(1, scal);
-    if (L == 2)
-      prolong_add<T, T>(g0, grids_[1], w0_, zc_, scal, false, st_);
-    else
-      prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, scal, false, st_);
+    const double cb = (double)grids_[1].n * nact * 3 * (L == 2 ? TB : VB);
+    clock.timed(HMG_K_PROLONG, vn * nact * 6 * TB + cb, st_, [&] {
+      if (L == 2)
+        prolong_add<T, T>(g0, grids_[1], w0_, zc_, scal, false, st_);
+      else
+        prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, scal, false, st_);
+    });
     clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 3 * (3 * TB + (qpr ? TB : 0)) + 7 * TB), st_, [&] {
       op0_post_smooth<T, V>(L0, w0_, r0, dinv0_, zout, qpr, scal, part_, nb);
     });
@@ -923,6 +930,7 @@ class Solver final : public SolverIface {
   ModeK<double> mk64_{};
   LoadTpl<T> tpl_{};
   LoadTpl<double> tpl64_{};
+  double* tplg_ = nullptr;  // tpl64_ in device memory (FP64 residual)
   LoadTpl<double> chh64_{};
   LoadTpl<float> chh32_{};
   bool fp16_ready_ = false;  // r_ holds the FP16 cast of the current solution
@@ -1201,7 +1209,7 @@ class BatchSolver {
       fin_mean(X.part_, nb, g0.n, X.aux_, st_);
       vec_mean_subtract<double>(g0, X.x_, X.aux_, st_);
       scal_set_all_active(X.aux_, st_);
-      op0_force_residual<float>(L64, X.tpl64_, X.x_, X.r_, X.aux_, X.part_, &nb);
+      op0_force_residual<float>(L64, X.tplg_, X.x_, X.r_, X.aux_, X.part_, &nb);
       fin_sum(X.part_, S_FF, nb, X.aux_, true, st_);
       fin_sum(X.part_, S_TRUE, nb, X.aux_, true, st_);
       HMG_TRY(X.read_scal(X.aux_, X.hscal_ + S_NSLOT * 8));
@@ -1285,7 +1293,7 @@ class BatchSolver {
     Op0Launch<double> L64{g0, X.mk64_, X.s64_, st_};
     X.set_mask(X.aux_, check);
     int nb = 0;
-    op0_force_residual<float>(L64, X.tpl64_, X.x_, X.r_, X.aux_, X.part_, &nb);
+    op0_force_residual<float>(L64, X.tplg_, X.x_, X.r_, X.aux_, X.part_, &nb);
     fin_sum(X.part_, S_TRUE, nb, X.aux_, false, st_);
     HMG_TRY(X.read_scal(X.aux_, X.hscal_ + S_NSLOT * 8));
     const double* ha = X.hscal_ + S_NSLOT * 8;

@@ -16,7 +16,7 @@ from . import _lib
 
 OK, E_INVALID, E_OOM, E_DEVICE, E_NOT_CONVERGED, E_STATE = range(6)
 KERNELS = {"matvec": 0, "residual": 1, "post_smooth": 2, "update": 3, "true_residual": 4,
-           "jacobi": 5, "gs_forward": 6, "gs_backward": 7}
+           "jacobi": 5, "gs_forward": 6, "gs_backward": 7, "prolong": 8}
 PRECISIONS = {"fp64": 0, "fp32": 1, "mixed_bf16": 2, "mixed_bf16_stencil": 4}
 SMOOTHERS = {"jacobi": 0, "gs": 1}
 SYMMETRIES = {"reflect3": 0, "reflect6": 1, "rotate3": 2}
