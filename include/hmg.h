@@ -129,7 +129,7 @@ typedef struct hmg_config {
  * hipStream_t (NULL = default stream).  Allocates the multigrid hierarchy and
  * the PCG work fields in device memory.  Fails with HMG_E_INVALID for a bad
  * configuration (shape, material, levels, or a coarsest grid above the direct
- * solver's limit of 3072 unknowns) and HMG_E_OOM if the device is too small. */
+ * solver's limit of 12288 unknowns, a 16^3 grid) and HMG_E_OOM if the device is too small. */
 hmg_status hmg_create(const hmg_config* cfg, void* hip_stream, hmg_ctx* out);
 
 /* Release every device buffer of the context.  NULL is accepted. */

@@ -581,7 +581,14 @@ __global__ void dinv_stencil_kernel(Grid g, const T* __restrict__ st, double ome
   }
 }
 
-// Dense coarsest matrix (row per thread), then vertex 0 pinned to the identity.
+__global__ void zero_kernel(int64_t count, double* __restrict__ A) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    A[i] = 0.0;
+}
+
+// Dense coarsest matrix (the three rows of a vertex per thread, added into a
+// cleared matrix), then vertex 0 pinned to the identity.
 template <typename T>
 __global__ void dense_kernel(Grid g, const T* __restrict__ st, double* __restrict__ A) {
   const int64_t N = 3 * g.n;
@@ -590,8 +597,6 @@ __global__ void dense_kernel(Grid g, const T* __restrict__ st, double* __restric
     const int gx = (int)(v % g.nx);
     const int gy = (int)((v / g.nx) % g.ny);
     const int gz = (int)(v / ((int64_t)g.nx * g.ny));
-    for (int p = 0; p < 3; ++p)
-      for (int64_t j = 0; j < N; ++j) A[(3 * v + p) * N + j] = 0.0;
     for (int d = 0; d < 27; ++d) {
       const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
       const int64_t w = modp(gx + dx, g.nx) +
@@ -640,6 +645,117 @@ __global__ void __launch_bounds__(1024) gj_kernel(int N, double* __restrict__ A,
       for (int j = lane; j < N; j += 64) row[j] = (j == k) ? -f * piv : row[j] - f * rk[j];
     }
     __syncthreads();
+  }
+}
+
+// Blocked Gauss-Jordan inverse for the larger coarsest grids, one panel of
+// GJ_B pivots at a time.  With the panel's rows and columns K and the rest I:
+//   A[K,K] <- P^-1,  A[K,I] <- P^-1 A[K,I],  A[I,K] <- -A[I,K] P^-1,
+//   A[I,I] <- A[I,I] - A[I,K] P^-1 A[K,I]      (P = A[K,K]),
+// which after the last panel leaves the inverse in A (no pivoting: A is SPD).
+constexpr int GJ_B = 32;
+
+// P^-1 of the panel's diagonal block (b <= GJ_B) by unblocked GJ in LDS.
+__global__ void __launch_bounds__(1024) gj_panel_inverse_kernel(int N, const double* __restrict__ A,
+                                                                int k0, int b,
+                                                                double* __restrict__ Pi) {
+  __shared__ double P[GJ_B][GJ_B + 1];
+  __shared__ double col[GJ_B], rowk[GJ_B];
+  const int t = threadIdx.x, r = t / GJ_B, c = t % GJ_B;
+  if (r < b && c < b) P[r][c] = A[(int64_t)(k0 + r) * N + k0 + c];
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    const double piv = 1.0 / P[k][k];
+    if (t < b) {
+      col[t] = P[t][k];
+      rowk[t] = P[k][t];
+    }
+    __syncthreads();
+    if (r < b && c < b) {
+      if (r == k)
+        P[r][c] = (c == k) ? piv : rowk[c] * piv;
+      else
+        P[r][c] = (c == k) ? -col[r] * piv : P[r][c] - col[r] * piv * rowk[c];
+    }
+    __syncthreads();
+  }
+  // entries beyond a ragged last panel are zero (the row-panel kernel sums
+  // over all GJ_B columns)
+  Pi[r * GJ_B + c] = (r < b && c < b) ? P[r][c] : 0.0;
+}
+
+// Save the old column panel: Cs[i][m] = A[i][k0 + m].
+__global__ void gj_save_columns_kernel(int N, const double* __restrict__ A, int k0, int b,
+                                       double* __restrict__ Cs) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)N * GJ_B;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / GJ_B), m = (int)(e % GJ_B);
+    Cs[e] = m < b ? A[(int64_t)i * N + k0 + m] : 0.0;
+  }
+}
+
+// Row panel: A[K, j] <- P^-1 A[K, j] (j outside K), A[K, K] <- P^-1.
+__global__ void gj_row_panel_kernel(int N, double* __restrict__ A, int k0, int b,
+                                    const double* __restrict__ Pi) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    if (j >= k0 && j < k0 + b) {
+      for (int m = 0; m < b; ++m) A[(int64_t)(k0 + m) * N + j] = Pi[m * GJ_B + (j - k0)];
+      continue;
+    }
+    double old[GJ_B];
+#pragma unroll
+    for (int l = 0; l < GJ_B; ++l) old[l] = l < b ? A[(int64_t)(k0 + l) * N + j] : 0.0;
+    for (int m = 0; m < b; ++m) {
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < GJ_B; ++l) a += Pi[m * GJ_B + l] * old[l];
+      A[(int64_t)(k0 + m) * N + j] = a;
+    }
+  }
+}
+
+// Trailing update of the rows outside K, a 64 x 64 tile per block (4 x 4 per
+// thread): A[i][j] <- [j outside K] A[i][j] - sum_m Cs[i][m] A[k0 + m][j].
+// For j in K the row panel holds P^-1, giving -A[I,K] P^-1.
+__global__ void __launch_bounds__(256) gj_update_kernel(int N, double* __restrict__ A, int k0,
+                                                        int b, const double* __restrict__ Cs) {
+  __shared__ double Ct[64][GJ_B + 1];
+  __shared__ double Rt[GJ_B][64 + 1];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * GJ_B; e += 256) {
+    const int ii = e / GJ_B, m = e % GJ_B;
+    Ct[ii][m] = (i0 + ii < N) ? Cs[(int64_t)(i0 + ii) * GJ_B + m] : 0.0;
+  }
+  for (int e = t; e < GJ_B * 64; e += 256) {
+    const int m = e / 64, jj = e % 64;
+    Rt[m][jj] = (m < b && j0 + jj < N) ? A[(int64_t)(k0 + m) * N + j0 + jj] : 0.0;
+  }
+  __syncthreads();
+  const int tx = t % 16, ty = t / 16;
+  double acc[4][4] = {};
+  for (int m = 0; m < GJ_B; ++m) {
+    double cv[4], rv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) cv[a] = Ct[ty * 4 + a][m];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = Rt[m][tx * 4 + q];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[a][q] += cv[a] * rv[q];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ty * 4 + a;
+    if (i >= N || (i >= k0 && i < k0 + b)) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tx * 4 + q;
+      if (j >= N) continue;
+      double* aij = A + (int64_t)i * N + j;
+      *aij = ((j >= k0 && j < k0 + b) ? 0.0 : *aij) - acc[a][q];
+    }
   }
 }
 
@@ -700,6 +816,81 @@ __global__ void __launch_bounds__(1024) coarse_solve_kernel(Grid g, const double
   for (int k = 0; k < 3; ++k)
     for (int v = threadIdx.x; v < n; v += blockDim.x)
       z[(int64_t)(c * 3 + k) * n + v] = from_d<T>(zl[3 * v + k] - m[k]);
+}
+
+// Coarsest solve for grids whose right-hand sides do not fit in LDS, in three
+// passes over global scratch (same steps as coarse_solve_kernel):
+// (1) the projected right-hand side X[c][i], zero at the pinned vertex;
+template <typename R>
+__global__ void __launch_bounds__(1024) cs_rhs_kernel(Grid g, const R* __restrict__ r,
+                                                      double* __restrict__ X, const double* scal) {
+  __shared__ double red[16];
+  const int c = blockIdx.x;
+  if (!case_on(scal, c)) return;
+  const int n = (int)g.n, N = 3 * n;
+  for (int k = 0; k < 3; ++k) {
+    double a = 0.0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) a += to_d(r[(int64_t)(c * 3 + k) * n + v]);
+    const double m = block_allsum(a, red) / n;
+    for (int v = threadIdx.x; v < n; v += blockDim.x)
+      X[(int64_t)c * N + 3 * v + k] =
+          (v == 0) ? 0.0 : to_d(r[(int64_t)(c * 3 + k) * n + v]) - m;
+  }
+}
+
+// (2) partial products Zp[jc][c][i] = sum over the jc-th slice of j of
+// Ainv[j][i] X[c][j] (column i of the symmetric inverse, as the LDS form
+// reads it), a thread per i, the slice of X staged in LDS;
+constexpr int CS_SLICES = 16;
+__global__ void __launch_bounds__(256) cs_gemv_kernel(int N, const double* __restrict__ Ainv,
+                                                      const double* __restrict__ X,
+                                                      double* __restrict__ Zp,
+                                                      const double* scal) {
+  extern __shared__ double xs[];  // [NCASE][len]
+  const int jc = blockIdx.y;
+  const int ja = (int)((int64_t)N * jc / CS_SLICES), jb = (int)((int64_t)N * (jc + 1) / CS_SLICES);
+  const int len = jb - ja;
+  bool on[NCASE];
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) on[c] = case_on(scal, c);
+  for (int e = threadIdx.x; e < NCASE * len; e += blockDim.x) {
+    const int c = e / len, j = e % len;
+    xs[e] = on[c] ? X[(int64_t)c * N + ja + j] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc[NCASE] = {};
+  for (int j = 0; j < len; ++j) {
+    const double a = Ainv[(int64_t)(ja + j) * N + i];
+#pragma unroll
+    for (int c = 0; c < NCASE; ++c) acc[c] += a * xs[c * len + j];
+  }
+#pragma unroll
+  for (int c = 0; c < NCASE; ++c) Zp[((int64_t)jc * NCASE + c) * N + i] = acc[c];
+}
+
+// (3) the slices summed in order, the result projected to zero mean per
+// component and stored.
+template <typename T>
+__global__ void __launch_bounds__(1024) cs_finish_kernel(Grid g, const double* __restrict__ Zp,
+                                                         T* __restrict__ z, const double* scal) {
+  __shared__ double red[16];
+  const int c = blockIdx.x;
+  if (!case_on(scal, c)) return;
+  const int n = (int)g.n, N = 3 * n;
+  auto zval = [&](int i) {
+    double a = 0.0;
+    for (int jc = 0; jc < CS_SLICES; ++jc) a += Zp[((int64_t)jc * NCASE + c) * N + i];
+    return a;
+  };
+  for (int k = 0; k < 3; ++k) {
+    double a = 0.0;
+    for (int v = threadIdx.x; v < n; v += blockDim.x) a += zval(3 * v + k);
+    const double m = block_allsum(a, red) / n;
+    for (int v = threadIdx.x; v < n; v += blockDim.x)
+      z[(int64_t)(c * 3 + k) * n + v] = from_d<T>(zval(3 * v + k) - m);
+  }
 }
 
 }  // namespace
@@ -793,20 +984,60 @@ void dinv_from_stencil(const Grid& g, const T* st, double omega, T* dinv, hipStr
 }
 template <typename T>
 void dense_from_stencil(const Grid& g, const T* st, double* A, hipStream_t stm) {
+  const int64_t N = 3 * g.n;
+  hipLaunchKernelGGL(zero_kernel, dim3(pw_blocks(N * N, 256, 8192)), dim3(256), 0, stm, N * N, A);
   hipLaunchKernelGGL(dense_kernel<T>, dim3(pw_blocks(g.n, 64, 4096)), dim3(64), 0, stm, g, st, A);
   hipLaunchKernelGGL(pin_kernel, dim3(pw_blocks(3 * g.n, 256, 4096)), dim3(256), 0, stm,
                      (int64_t)(3 * g.n), A);
 }
+
+// Coarsest grids of up to SMALL_COARSE_DOF unknowns use the one-workgroup
+// inverse and keep their right-hand sides in LDS; larger ones (up to
+// MAX_COARSE_DOF) the blocked inverse and the three-pass solve.
+constexpr int SMALL_COARSE_DOF = 3072;
+
+int64_t coarse_scratch_doubles(int N) {
+  return (int64_t)N * GJ_B + GJ_B * GJ_B + (int64_t)NCASE * N * (1 + CS_SLICES);
+}
+
 void gauss_jordan_inverse(int N, double* A, hipStream_t stm) {
-  // scratch column lives right after the matrix (allocated by the caller)
-  hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(1024), 0, stm, N, A, A + (int64_t)N * N);
+  // scratch lives right after the matrix (coarse_scratch_doubles, allocated by the caller)
+  double* scr = A + (int64_t)N * N;
+  if (N <= SMALL_COARSE_DOF) {
+    hipLaunchKernelGGL(gj_kernel, dim3(1), dim3(1024), 0, stm, N, A, scr);
+    return;
+  }
+  double* Cs = scr;
+  double* Pi = scr + (int64_t)N * GJ_B;
+  const dim3 tiles((N + 63) / 64, (N + 63) / 64);
+  for (int k0 = 0; k0 < N; k0 += GJ_B) {
+    const int b = std::min(GJ_B, N - k0);
+    hipLaunchKernelGGL(gj_panel_inverse_kernel, dim3(1), dim3(GJ_B * GJ_B), 0, stm, N, A, k0, b,
+                       Pi);
+    hipLaunchKernelGGL(gj_save_columns_kernel, dim3(pw_blocks((int64_t)N * GJ_B, 256, 4096)),
+                       dim3(256), 0, stm, N, A, k0, b, Cs);
+    hipLaunchKernelGGL(gj_row_panel_kernel, dim3((N + 255) / 256), dim3(256), 0, stm, N, A, k0, b,
+                       Pi);
+    hipLaunchKernelGGL(gj_update_kernel, tiles, dim3(256), 0, stm, N, A, k0, b, Cs);
+  }
 }
 template <typename R, typename T>
 void coarse_solve(const Grid& g, const double* Ainv, const R* r, T* z, const double* scal,
                   hipStream_t stm) {
-  const size_t shm = sizeof(double) * 6 * g.n;
-  hipLaunchKernelGGL((coarse_solve_kernel<R, T>), dim3(NCASE), dim3(1024), shm, stm, g, Ainv, r, z,
-                     scal);
+  const int N = (int)(3 * g.n);
+  if (N <= SMALL_COARSE_DOF) {
+    const size_t shm = sizeof(double) * 6 * g.n;
+    hipLaunchKernelGGL((coarse_solve_kernel<R, T>), dim3(NCASE), dim3(1024), shm, stm, g, Ainv, r,
+                       z, scal);
+    return;
+  }
+  double* X = const_cast<double*>(Ainv) + (int64_t)N * N + (int64_t)N * GJ_B + GJ_B * GJ_B;
+  double* Zp = X + (int64_t)NCASE * N;
+  hipLaunchKernelGGL((cs_rhs_kernel<R>), dim3(NCASE), dim3(1024), 0, stm, g, r, X, scal);
+  const size_t shm = sizeof(double) * NCASE * ((N + CS_SLICES - 1) / CS_SLICES);
+  hipLaunchKernelGGL(cs_gemv_kernel, dim3((N + 255) / 256, CS_SLICES), dim3(256), shm, stm, N,
+                     Ainv, X, Zp, scal);
+  hipLaunchKernelGGL((cs_finish_kernel<T>), dim3(NCASE), dim3(1024), 0, stm, g, Zp, z, scal);
 }
 
 #define HMG_INSTKC(T, W)                                                                         \

@@ -305,7 +305,10 @@ template <typename T>
 void dinv_from_stencil(const Grid& g, const T* st, double omega, T* dinv, hipStream_t stm);
 template <typename T>
 void dense_from_stencil(const Grid& g, const T* st, double* A, hipStream_t stm);
+// In-place inverse of the N x N SPD matrix A; A must be followed by
+// coarse_scratch_doubles(N) doubles of scratch, which coarse_solve also uses.
 void gauss_jordan_inverse(int N, double* A, hipStream_t stm);
+int64_t coarse_scratch_doubles(int N);
 template <typename R, typename T>
 void coarse_solve(const Grid& g, const double* Ainv, const R* r, T* z, const double* scal,
                   hipStream_t stm);

@@ -27,7 +27,7 @@ using namespace hmg;
 
 namespace {
 
-constexpr int MAX_COARSE_DOF = 3072;  // dense inverse of the coarsest grid
+constexpr int MAX_COARSE_DOF = 12288;  // dense inverse of the coarsest grid (16^3 vertices)
 
 struct Status {
   hmg_status code = HMG_OK;
@@ -256,7 +256,8 @@ class Solver final : public SolverIface {
     // the coarsest correction is the largest, smoothest field of the cycle and
     // is multiplied by K after prolongation: it keeps the arithmetic type
     if (L > 1) zc_ = (T*)A(sizeof(T) * NCASE * 3 * gL.n);
-    Ainv_ = (double*)A(sizeof(double) * ((size_t)ncdof_ * ncdof_ + ncdof_));
+    Ainv_ = (double*)A(sizeof(double) *
+                       ((size_t)ncdof_ * ncdof_ + (size_t)coarse_scratch_doubles(ncdof_)));
     if (L == 1) st0_ = (T*)A(sizeof(T) * 243 * g0.n);
     stride_ = std::max(op0_blocks_per_case(g0), 4096);
     if (gs_) stride_ = std::max(stride_, 4 * gs0_blocks_per_case(g0));

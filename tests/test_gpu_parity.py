@@ -281,9 +281,28 @@ def test_error_paths():
     assert err.value.status == E_INVALID
     ctx.transfer(0, 1, e, out=buf[:-1])
     with pytest.raises(HmgError):
-        ctx_for((16, 16, 6), "fp32")       # 6 -> 3 stops coarsening; coarsest too large?
+        ctx_for((48, 48, 6), "fp32")       # 6 -> 3 stops coarsening: 41472 unknowns, too many
     with pytest.raises(HmgError):
         ctx_for((3, 16, 16), "fp32")
+
+
+@pytest.mark.parametrize("shape,levels", [((9, 12, 12), 0), ((16, 16, 6), 0), ((16, 16, 16), 1)])
+def test_large_coarsest_direct_solve(shape, levels):
+    """One-level grids above the one-workgroup inverse's 3072 unknowns use the
+    blocked Gauss-Jordan inverse (panels of 32 pivots, 64 x 64 update tiles) and
+    the three-pass coarsest solve: 3888 unknowns (a ragged last panel and ragged
+    tiles), 4608, and 12288 (a 16^3 grid, the largest coarsest grid).  The
+    preconditioner is then the exact inverse: PCG converges in one iteration (two
+    allowed) and C^H equals the oracle's."""
+    rho = f32(0.3 + I.uniform_density(shape, 23))
+    ctx = ctx_for(shape, "fp64", levels=levels)
+    assert ctx.num_levels() == 1
+    ctx.set_density(dev(rho))
+    res = ctx.solve_cases(1e-10, 20)
+    print(shape, "iters", res.iters.tolist(), flush=True)
+    assert res.converged and (res.iters <= 2).all(), res
+    _, u, Cref = oracle_solution(rho.astype(np.float64), shape)
+    assert rel(ctx.elastic_tensor(), Cref) < 1e-10
 
 
 def test_deterministic_bitwise():
