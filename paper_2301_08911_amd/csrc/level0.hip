@@ -244,10 +244,13 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
 #pragma unroll
   for (int sl = 0; sl < S::NSLOT; ++sl) {
     const int i = tid + sl * S::NTHR;
-    ld_ok[sl] = i < S::NVTX;
-    const int ii = ld_ok[sl] ? i : 0;
+    const int ii = i < S::NVTX ? i : 0;
     const int py = ii / S::PX, px = ii - py * S::PX;
     const int ux = x0 - 1 + px, uy = y0 - 1 + py;
+    // A tile at the high x or y end of the grid needs its staged plane only up
+    // to the one-vertex halo (which wraps to 0); beyond it the plane would hold
+    // copies of the grid's first columns or rows, which no owned vertex uses.
+    ld_ok[sl] = i < S::NVTX && ux <= g.nx && uy <= g.ny;
     ld_gx[sl] = modp(ux, g.nx);
     ld_gy[sl] = modp(uy, g.ny);
     ld_xy[sl] = (uint32_t)ld_gx[sl] + (uint32_t)g.nx * (uint32_t)ld_gy[sl];
