@@ -178,10 +178,11 @@ __global__ void stencil_kernel(Grid g, const W* __restrict__ st, const T* __rest
 }
 
 // The same three modes for a pair of vertices (x0, x0 + 1) per thread, used
-// for FP32 stencils on rows of even length.  The
+// for FP32 and bf16 stencils on rows of even length.  The
 // two vertices share their neighbour columns: per neighbour row and component
 // one paired load (x0, x0 + 1) and two single loads (x0 - 1, x0 + 2) replace
 // six loads, and every stencil coefficient of the pair is one paired load.
+// Rounded stencils skip the centre block and use the difference form.
 template <typename T, typename W, int MODE>
 __global__ void __launch_bounds__(256)
 stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u, const T* __restrict__ r,
@@ -205,19 +206,38 @@ stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u, const
       for (int c = 0; c < NCASE; ++c) acc[h][c][0] = acc[h][c][1] = acc[h][c][2] = A(0);
     const int xm = x0 == 0 ? g.nx - 1 : x0 - 1;
     const int xp = x0 + 2 == g.nx ? 0 : x0 + 2;
+    constexpr bool kDiff = kCentreFromSum<W>;
+    A uc[2][NCASE][3];  // u at the pair, subtracted in the difference form
+    if (kDiff) {
+#pragma unroll
+      for (int c = 0; c < NCASE; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const Pair<T> own = *reinterpret_cast<const Pair<T>*>(u + (size_t)(c * 3 + k) * n + i);
+          uc[0][c][k] = (A)own.v[0];
+          uc[1][c][k] = (A)own.v[1];
+        }
+    }
     for (int a = 0; a < 9; ++a) {
       int y = gy + a % 3 - 1, z = gz + a / 3 - 1;
       y = y < 0 ? y + g.ny : (y == g.ny ? 0 : y);
       z = z < 0 ? z + g.nz : (z == g.nz ? 0 : z);
       const int rb = g.nx * (y + g.ny * z);
-      // coefficients of both vertices for the three x offsets of this row
+      // coefficients of both vertices for the three x offsets of this row (a
+      // rounded stencil's centre block is zero here: the difference form)
       A K[3][2][9];
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
         const W* sd = st + (size_t)((3 * a + dx) * 9) * n;
+        const bool skip = kDiff && a == 4 && dx == 1;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-          const Pair<W> kp = *reinterpret_cast<const Pair<W>*>(sd + (size_t)t * n + i);
+          Pair<W> kp;
+          if (skip) {
+            kp.v[0] = kp.v[1] = W(0.0f);
+          } else {
+            kp = *reinterpret_cast<const Pair<W>*>(sd + (size_t)t * n + i);
+          }
           K[dx][0][t] = (A)kp.v[0];
           K[dx][1][t] = (A)kp.v[1];
         }
@@ -239,7 +259,9 @@ stencil2_kernel(Grid g, const W* __restrict__ st, const T* __restrict__ u, const
 #pragma unroll
           for (int dx = 0; dx < 3; ++dx) {
             const A* Kd = K[dx][h];
-            const A* v = uu[h + dx];
+            A v[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[k] = kDiff ? uu[h + dx][k] - uc[h][c][k] : uu[h + dx][k];
             acc[h][c][0] += Kd[0] * v[0] + Kd[1] * v[1] + Kd[2] * v[2];
             acc[h][c][1] += Kd[3] * v[0] + Kd[4] * v[1] + Kd[5] * v[2];
             acc[h][c][2] += Kd[6] * v[0] + Kd[7] * v[1] + Kd[8] * v[2];
@@ -895,12 +917,12 @@ __global__ void __launch_bounds__(1024) cs_finish_kernel(Grid g, const double* _
 
 }  // namespace
 
-// Paired-vertex stencil passes: FP32 stencils with FP32 or bf16 vectors, and
+// Paired-vertex stencil passes: FP32 or bf16 stencils with FP32 or bf16 vectors, and
 // an even row.
 template <typename T, typename W>
 inline bool use_pairs(const Grid& g) {
   return (std::is_same<T, float>::value || std::is_same<T, bf16>::value) &&
-         std::is_same<W, float>::value && g.nx % 2 == 0;
+         (std::is_same<W, float>::value || std::is_same<W, bf16>::value) && g.nx % 2 == 0;
 }
 template <typename T, typename W>
 void kc_apply(const Grid& g, const W* st, const T* u, T* y, hipStream_t s) {
