@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
-    ap.add_argument("--forms", default="plain,plain_gs,mixed_bf16,cold,learned",
+    ap.add_argument("--forms", default="plain,plain_gs,mixed_bf16,mixed_bf16_stencil,cold,learned",
                     help="comma list of plain, mixed_bf16, mixed_bf16_stencil, learned, cold, "
                          "each optionally with the suffix _gs (eight-colour Gauss-Seidel smoother "
                          "instead of damped Jacobi) (the first is the headline and runs --warmup + --steps steps; the "

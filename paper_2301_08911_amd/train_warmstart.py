@@ -66,6 +66,8 @@ def generate(sizes, counts, base_seed, tol, log):
             inp, tgt, it = solve_pair(n, base_seed + 1000 * n + k, tol)
             xs.append(inp)
             ys.append(tgt)
+            if (k + 1) % 100 == 0:
+                log(f"  {k + 1} of {cnt} cells of {n}^3 ({time.perf_counter() - t0:.1f} s)")
         D = xs[0].shape[-1]
         data[D] = data.get(D, ([], []))
         data[D][0].extend(xs)
