@@ -77,15 +77,27 @@ __device__ __forceinline__ void block_apply(const A (&D)[6], A r0, A r1, A r2, A
   o[2] = D[5] * r0 + D[4] * r1 + D[2] * r2;
 }
 
+// Offset visited i-th: each neighbour row (dy, dz) in turn, its centre column
+// dx = 1 first, then dx = 0 and dx = 2 (d = dx + 3 (dy + 1) + 9 (dz + 1)).
+__host__ __device__ constexpr int row_centre_first(int i) {
+  return 3 * (i / 3) + (i % 3 == 0 ? 1 : (i % 3 == 1 ? 0 : 2));
+}
+
 template <class F, int... I>
 __device__ __forceinline__ void static_for27_impl(F& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
+  (f(std::integral_constant<int, row_centre_first(I)>{}), ...);
 }
-// f(std::integral_constant<int, d>) for d = 0..26 in order.
+// f(std::integral_constant<int, d>) for the 27 offsets d, row by row, the
+// centre column of each row first.
 template <class F>
 __device__ __forceinline__ void static_for27(F& f) {
   static_for27_impl(f, std::make_integer_sequence<int, 27>{});
 }
+
+template <typename T>
+struct alignas(2 * sizeof(T)) VPair {
+  T a, b;
+};
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -211,11 +223,11 @@ struct SrcStored {
 // pair, the first x parity, an LDS barrier, then the second.  With `dot`, the
 // block partials of (r - m).z (S_RZNEW) and q.z (S_QZ) of the finished rows
 // go to column k * gridDim.x + bx of `part`.
-template <typename V, class Src>
+template <typename V, class Src, int first>
 __global__ void __launch_bounds__(GS_THREADS)
 gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restrict__ mean,
                V* __restrict__ z, const V* __restrict__ q, const double* __restrict__ scal,
-               Partials part, int dot, int k, int first, int fresh, int rpb) {
+               Partials part, int dot, int k, int fresh, int rpb) {
   using A = typename Acc<V>::type;
   constexpr bool kDiff = Src::kDiff;
   __shared__ A nw[GS_ITEMSC][NCASE][3];
@@ -236,7 +248,8 @@ gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restric
   for (int c = 0; c < NCASE; ++c) acc_rz[c] = acc_qz[c] = 0.0;
   for (int rb = rb0; rb < rb1; rb += rs) {
     const int nitems = min(rs, rb1 - rb) * np;
-#pragma unroll 1
+    // both steps unrolled: the x parity is a compile-time constant in each
+#pragma unroll
     for (int step = 0; step < 2; ++step) {
       const int xpar = step == 0 ? first : 1 - first;
       const int w = threadIdx.x;
@@ -261,6 +274,14 @@ gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restric
 #pragma unroll
         for (int c = 0; c < NCASE; ++c) acc[c][0] = acc[c][1] = acc[c][2] = A(0);
         A Kc[9];
+        // In a neighbour row (not the own row) the centre column is read as
+        // the aligned pair (x - xpar, x - xpar + 1), which also holds the
+        // column on the other side of x from the pair's start: x + 1 for an
+        // even x, x - 1 for an odd one.  That value is kept for the row's next
+        // offset, and only the remaining column is a single load: two loads
+        // per row and component instead of three.
+        A kept[NCASE][3];
+        const int pb = x - xpar;
         // the 27 offsets; d is a compile-time constant in every iteration
         auto visit = [&](auto dconst) {
           constexpr int d = decltype(dconst)::value;
@@ -277,6 +298,8 @@ gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restric
           if (zero && !from_lds && !(own && dx == 1)) return;
           const int64_t rbase =
               (int64_t)g.nx * (wrap(y + dy, g.ny) + (int64_t)g.ny * wrap(zz + dz, g.nz));
+          // the kept pair half is the x - 1 column for an odd x, x + 1 for an even x
+          const bool use_kept = !own && dx != 1 && (dx == 0) == (xpar == 1);
 #pragma unroll
           for (int c = 0; c < NCASE; ++c) {
             A u[3];
@@ -290,6 +313,17 @@ gs_pair_kernel(Grid g, Src src, const V* __restrict__ r, const double* __restric
             } else if (zero) {
 #pragma unroll
               for (int kk = 0; kk < 3; ++kk) u[kk] = A(0);
+            } else if (!own && dx == 1) {
+#pragma unroll
+              for (int kk = 0; kk < 3; ++kk) {
+                const VPair<V> pr =
+                    *reinterpret_cast<const VPair<V>*>(z + (int64_t)(c * 3 + kk) * n + rbase + pb);
+                u[kk] = (A)(xpar ? pr.b : pr.a);
+                kept[c][kk] = (A)(xpar ? pr.a : pr.b);
+              }
+            } else if (use_kept) {
+#pragma unroll
+              for (int kk = 0; kk < 3; ++kk) u[kk] = kept[c][kk];
             } else {
 #pragma unroll
               for (int kk = 0; kk < 3; ++kk)
@@ -382,9 +416,13 @@ void gs0_sweep(const Grid& g, const double* k0v, const T* s, const T* r, const d
   const int nblk = (gs_rows(g) + rpb - 1) / rpb;
   for (int i = 0; i < 4; ++i) {
     const int k = forward ? i : 3 - i;
-    hipLaunchKernelGGL((gs_pair_kernel<T, SrcLevel0<T>>), dim3(nblk), dim3(GS_THREADS), 0, st, g,
-                       src, r, mean, z, q, scal, part, nblk_out ? 1 : 0, k, forward ? 0 : 1,
-                       (forward && fresh) ? 1 : 0, rpb);
+    if (forward)
+      hipLaunchKernelGGL((gs_pair_kernel<T, SrcLevel0<T>, 0>), dim3(nblk), dim3(GS_THREADS), 0, st,
+                         g, src, r, mean, z, q, scal, part, nblk_out ? 1 : 0, k, fresh ? 1 : 0,
+                         rpb);
+    else
+      hipLaunchKernelGGL((gs_pair_kernel<T, SrcLevel0<T>, 1>), dim3(nblk), dim3(GS_THREADS), 0, st,
+                         g, src, r, mean, z, q, scal, part, nblk_out ? 1 : 0, k, 0, rpb);
   }
   if (nblk_out) *nblk_out = 4 * nblk;
 }
@@ -397,9 +435,13 @@ void gsc_sweep(const Grid& g, const W* stc, const W* dinv, const V* r, const dou
   const int nblk = (gs_rows(g) + rpb - 1) / rpb;
   for (int i = 0; i < 4; ++i) {
     const int k = forward ? i : 3 - i;
-    hipLaunchKernelGGL((gs_pair_kernel<V, SrcStored<W>>), dim3(nblk), dim3(GS_THREADS), 0, st, g,
-                       src, r, mean, z, (const V*)nullptr, scal, Partials{}, 0, k,
-                       forward ? 0 : 1, (forward && fresh) ? 1 : 0, rpb);
+    if (forward)
+      hipLaunchKernelGGL((gs_pair_kernel<V, SrcStored<W>, 0>), dim3(nblk), dim3(GS_THREADS), 0, st,
+                         g, src, r, mean, z, (const V*)nullptr, scal, Partials{}, 0, k,
+                         fresh ? 1 : 0, rpb);
+    else
+      hipLaunchKernelGGL((gs_pair_kernel<V, SrcStored<W>, 1>), dim3(nblk), dim3(GS_THREADS), 0, st,
+                         g, src, r, mean, z, (const V*)nullptr, scal, Partials{}, 0, k, 0, rpb);
   }
 }
 
