@@ -187,14 +187,33 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return s;
 }
 
-// Block index -> (case, tile).  Workgroups are dispatched to the 8 XCDs round
-// robin, so consecutive logical indices are gathered on one XCD: the six cases
-// of a tile (which share s) and neighbouring tiles (which share halos) then
-// meet in the same L2.
+// Block index -> work item.  Workgroups are dispatched to the 8 XCDs round
+// robin, so consecutive logical indices are gathered on one XCD, where they
+// run in index order (one block per CU at a time).
 __device__ __forceinline__ int logical_block() {
   const int nb = gridDim.x, b = blockIdx.x;
   const int q = nb >> 3, r = nb & 7, xcd = b & 7;
   return xcd * q + (xcd < r ? xcd : r) + (b >> 3);
+}
+
+// Work item -> (load case, tile).  Consecutive items take a group of G load
+// cases over a whole row of x-tiles, then the next group of the same row: the
+// blocks resident on an XCD at one time then cover every x-tile of a row, so
+// the 128-byte lines at the tile boundaries (a staged row of 65 values spans
+// three of them) are fetched once for both neighbours, and a group's cases
+// share s.  Measured at 512^3 against six cases per tile with x-tiles in turn:
+// G = 2 took the FP32 matvec / residual / post-smooth from 13.8 / 9.1 / 10.8 to
+// 12.1 / 8.0 / 10.3 ms (matvec reads 36.6 -> 31.9 GB); the FP64 residual (63 x 7
+// tiles) is fastest with G = 3 (14.4 -> 11.4 ms).
+template <typename T>
+__device__ __forceinline__ void item_tile(int j, int ntx, int& c, int& tile) {
+  constexpr int G = sizeof(T) == 8 ? 3 : 2;
+  constexpr int NG = NCASE / G;
+  static_assert(NG * G == NCASE, "case groups must tile the load cases");
+  const int r = j / G;
+  const int q = r / ntx;  // NG * (tile row) + group
+  c = j % G + G * (q % NG);
+  tile = r % ntx + ntx * (q / NG);
 }
 
 template <int V>
@@ -210,7 +229,8 @@ struct Op0Waves {
   static constexpr int value = sizeof(T) == 4 ? HMG_OP0_WAVES : 2;
 };
 
-// One work item of a level-0 pass: case j % 6 of tile j / 6 of one cell.
+// One work item of a level-0 pass: one load case of one tile of one cell
+// (item_tile).
 template <typename T, class Op>
 __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const TileGeom& tg,
                                          const ModeK<T>& mk, const T* __restrict__ s, int j) {
@@ -219,8 +239,8 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   __shared__ T rowc[2][3][S::TYE][S::TXE];
   __shared__ double red[S::NTHR / 64];
 
-  const int c = j % NCASE;
-  const int tile = j / NCASE;
+  int c, tile;
+  item_tile<T>(j, tg.ntx, c, tile);
   if (!op_in.active(c)) return;
   // Per-case scalars are read once, before any store of the kernel could be
   // taken to alias them.
@@ -422,9 +442,9 @@ op0_kernel(Op op, Grid g, TileGeom tg, ModeK<T> mk, const T* __restrict__ s) {
 
 // Batched form: one persistent grid works through the items of many cells.
 // Items are ordered cell by cell (largest cells first) and split into eight
-// contiguous ranges, one per XCD, so that the six cases of a tile and
-// neighbouring tiles still meet in one L2; the blocks of an XCD take the items
-// of its range round robin.
+// contiguous ranges, one per XCD, so that the items that item_tile puts next
+// to each other still meet in one L2; the blocks of an XCD take the items of
+// its range round robin.
 template <typename T, class Op>
 struct Op0Cell {
   Op op;
