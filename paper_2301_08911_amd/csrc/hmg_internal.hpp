@@ -150,11 +150,17 @@ void op0_matvec_p(const Op0Launch<T>& L, const V* z, const V* pold, V* pnew, T* 
 // multiplied by K).
 template <typename T, typename V>
 void op0_residual(const Op0Launch<T>& L, const T* r, const T* z0, V* t, const double* scal);
-// zout = z1 + Dinv ((r - m) - K z1); partial (r - m).zout in S_RZNEW and, if
-// q is given, q.zout in S_QZ.
+// Damped block Jacobi at level 0: the diagonal (dd) and off-diagonal (oo) entry
+// of K0's diagonal blocks, and the damping factor.
+struct BlockDiag0 {
+  double dd, oo, omega;
+};
+// zout = z1 + omega D^-1 ((r - m) - K z1), D the vertex's diagonal block of K
+// formed in the kernel from s; partial (r - m).zout in S_RZNEW and, if q is
+// given, q.zout in S_QZ.
 template <typename T, typename V>
-void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
-                     const T* q, const double* scal, Partials part, int* nblk_out);
+void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const BlockDiag0& bd,
+                     T* zout, const T* q, const double* scal, Partials part, int* nblk_out);
 // r = f - K x evaluated in FP64 (x, s and the constants in double), stored as R.
 // tplg: the FP64 load template g[c][a][k] (LoadTpl layout) in device memory.
 template <typename R>
@@ -165,8 +171,8 @@ int op0_blocks_per_case(const Grid& g);
 
 // Batched level-0 passes (FP32) over many cells in one persistent launch.
 // Vectors per kind:  matvec: in0 z, in1 p_old, out0 p_new, out1 q;
-// residual: in0 r, in1 z0, out0 t;  post-smooth: in0 z1, in1 r, in2 dinv,
-// in3 q (optional), out0 z.
+// residual: in0 r, in1 z0, out0 t;  post-smooth: in0 z1, in1 r, in3 q
+// (optional), out0 z, and bd.
 enum Op0BatchKind { OP0B_MATVEC = 0, OP0B_RESIDUAL = 1, OP0B_POST_SMOOTH = 2 };
 struct Op0BatchCell {
   Grid g;
@@ -176,6 +182,7 @@ struct Op0BatchCell {
   float *out0, *out1;
   const double* scal;
   Partials part;
+  BlockDiag0 bd;  // post-smooth only
 };
 struct Op0BatchPlan;
 // Uploads the per-cell descriptors and the item list; `grid` blocks (<= 0: one
@@ -196,9 +203,11 @@ void forcing(const Grid& g, const LoadTpl<double>& tpl, const double* s, R* f, P
 template <typename T>
 void simp_scale(const Grid& g, const float* rho, T* s, T* rho_keep, double* s64, double* rho64,
                 double E0, double Emin, double penal, int* bad, hipStream_t st);
+// z0 = omega D^-1 (r - m) at level 0 for the active cases, D the vertex's
+// diagonal block of K formed from s (m from `mean` slots S_MEAN*, NULL: none).
 template <typename T>
-void dinv_level0(const Grid& g, const T* s, double dd, double oo, double omega, T* dinv,
-                 hipStream_t st);
+void jacobi0_level0(const Grid& g, const T* s, const BlockDiag0& bd, const T* r, T* z,
+                    const double* scal, const double* mean, hipStream_t st);
 template <typename T>
 void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipStream_t stm);
 
@@ -219,18 +228,19 @@ template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);
 // Batched FP32 pointwise passes over many cells (update grid: nblk x cells*6,
 // one load case per block row; Jacobi grid: nblk x cells):
-// update: x += alpha p, r -= alpha q (+ partials);  jacobi: z = Dinv (r - m),
-// m from the cell's scal.
+// update: x += alpha p, r -= alpha q (+ partials);  jacobi (level 0, grid rows
+// per block): z = omega D^-1 (r - m), D formed from s, m from the cell's scal.
 struct PwBatchCell {
   Grid g;
   double* x;
   const float* p;
   float* r;
   const float* q;
-  const float* dinv;
+  const float* s;  // element scales (level-0 Jacobi)
   float* z;
   const double* scal;
   Partials part;
+  BlockDiag0 bd;  // level-0 Jacobi
 };
 void update_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st);
 void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st);

@@ -219,6 +219,56 @@ __device__ __forceinline__ void item_tile(int j, int ntx, int& c, int& tile) {
 template <int V>
 using Par = std::integral_constant<int, V>;
 
+// Ops that declare DIAG = true receive, at each owned vertex, the four numbers
+// that fix the vertex's diagonal block sum_e s_e K0[a_e, a_e] (Sec. 4.2): with
+// the eight elements e at offsets d in {-1, 0}^3 and the sign t_i = +1 for
+// d_i = -1, -1 for d_i = 0, the block is dd * S on the diagonal and
+// oo * M_ij off it, where S = sum s_e and M_ij = sum s_e t_i t_j (the sign
+// pattern of K0's diagonal blocks under the cube's reflections).  They arrive
+// as dg = {S, M_xy, M_yz, M_xz}.
+template <class Op, class = void>
+struct OpDiag : std::false_type {};
+template <class Op>
+struct OpDiag<Op, std::void_t<decltype(Op::DIAG)>> : std::bool_constant<Op::DIAG> {};
+
+// omega (dd S I + oo M)^-1 for the modes dg = {S, M_xy, M_yz, M_xz} (OpDiag),
+// by cofactors over the determinant, as d = {xx, yy, zz, xy, yz, xz}.
+template <typename T>
+__device__ __forceinline__ void damped_block_inverse(T dd, T oo, T omega, const T (&dg)[4],
+                                                     T (&d)[6]) {
+  const T d0 = dd * dg[0];
+  const T d01 = oo * dg[1], d12 = oo * dg[2], d02 = oo * dg[3];
+  const T c00 = d0 * d0 - d12 * d12, c11 = d0 * d0 - d02 * d02, c22 = d0 * d0 - d01 * d01;
+  const T c01 = d02 * d12 - d01 * d0, c12 = d01 * d02 - d0 * d12, c02 = d01 * d12 - d02 * d0;
+  const T f = omega / (d0 * c00 + d01 * c01 + d02 * c02);
+  d[0] = f * c00;
+  d[1] = f * c11;
+  d[2] = f * c22;
+  d[3] = f * c01;
+  d[4] = f * c12;
+  d[5] = f * c02;
+}
+
+// 2x2 modes {sum, x, y, xy} of one element plane at a vertex, from the x-pair
+// sum a and difference b of element row y - 1 (au, bu; t_y = +1) and row y
+// (t_y = -1); each pair is s(x - 1) +- s(x), t_x = +1 for x - 1.
+template <typename T>
+__device__ __forceinline__ void plane_modes2(T au, T bu, T a, T b, T (&dm)[4]) {
+  dm[0] = au + a;
+  dm[1] = bu + b;
+  dm[2] = au - a;
+  dm[3] = bu - b;
+}
+
+// Vertex modes from the plane modes of element planes z - 1 (t_z = +1) and z.
+template <typename T>
+__device__ __forceinline__ void vertex_modes(const T (&lo)[4], const T (&hi)[4], T (&dg)[4]) {
+  dg[0] = lo[0] + hi[0];
+  dg[1] = lo[3] + hi[3];
+  dg[2] = lo[2] - hi[2];
+  dg[3] = lo[1] - hi[1];
+}
+
 // Occupancy target of the level-0 kernels (waves per SIMD), which bounds their
 // register budget: 512 / waves VGPRs.
 #ifndef HMG_OP0_WAVES
@@ -238,6 +288,10 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   __shared__ T plane[2][3][S::PY][S::PX];
   __shared__ T rowc[2][3][S::TYE][S::TXE];
   __shared__ double red[S::NTHR / 64];
+  // Diagonal modes (OpDiag): the x-pair sum and difference of s in each element
+  // row, handed to the row above.
+  constexpr bool DIAG = OpDiag<Op>::value;
+  __shared__ T sab[2][2][DIAG ? S::TYE : 1][DIAG ? S::TXE : 1];
 
   int c, tile;
   item_tile<T>(j, tg.ntx, c, tile);
@@ -337,6 +391,9 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
   // traffic.
   double acc0 = 0.0, acc1 = 0.0;
   T ta[4][3], tb[4][3], ga[4][3], rq[3], ucur[3], uprev[3];
+  // OpDiag: x-pair sum / difference of s in this thread's element row, latest
+  // element plane; the 2x2 modes {sum, x, y, xy} of the element plane before.
+  T ab[2] = {T(0), T(0)}, dm_prev[4] = {T(0), T(0), T(0), T(0)};
   typename Op::ERaw ea, eb;
   T sa, sb;
   // Vertex plane zu lives in raw set (zu - z0 + 1) & 1.  The issue order of
@@ -375,11 +432,28 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
     fetch_plane(min(ez + 3, z1), rawn);  // staged for ez+3 <= z1
     __builtin_amdgcn_sched_barrier(0);
     lds_barrier();
+    T dg[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (DIAG) {
+      if (ez >= z0) {
+        // 2x2 modes of element plane ez - 1 at vertex (ex, ey): element row
+        // ey - 1 (t_y = +1, from the row below in LDS) and row ey (t_y = -1).
+        const int lyu = ly > 0 ? ly - 1 : 0;
+        T dm[4];
+        plane_modes2(sab[cb][0][lyu][lx], sab[cb][1][lyu][lx], ab[0], ab[1], dm);
+        // vertex plane ez - 1 lies between element planes ez - 2 and ez - 1
+        vertex_modes(dm_prev, dm, dg);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dm_prev[k] = dm[k];
+      }
+    }
     if (ez > z0 && ez <= z1 && outv) {
       T ku[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) ku[k] = rq[k] + rowc[cb][k][ly - 1][lx];
-      op.store(c, nxy * (ez - 1), exy, ex, ey, ez - 1, ku, uprev, e_old, acc0, acc1);
+      if constexpr (DIAG)
+        op.store_diag(c, nxy * (ez - 1), exy, ku, uprev, e_old, dg, acc0, acc1);
+      else
+        op.store(c, nxy * (ez - 1), exy, ex, ey, ez - 1, ku, uprev, e_old, acc0, acc1);
     }
     const T se = s_old;
     if (ez < z1) {
@@ -414,6 +488,14 @@ __device__ __forceinline__ void op0_body(const Op& op_in, const Grid& g, const T
       for (int k = 0; k < 3; ++k) {
         uprev[k] = ucur[k];
         ucur[k] = unext[k];
+      }
+      if constexpr (DIAG) {
+        // element (ex - 1, ey) has t_x = +1, element (ex, ey) t_x = -1
+        const T sl = from_left(se);
+        ab[0] = sl + se;
+        ab[1] = sl - se;
+        sab[pb][0][ly][lx] = ab[0];
+        sab[pb][1][ly][lx] = ab[1];
       }
     }
   };
@@ -605,22 +687,25 @@ struct OpResidual {
   }
 };
 
-// Post-smoothing: zout = z1 + D^-1 ((r - m) - K z1), acc (r - m).zout.  z1 is
-// the pre-smoothed correction plus the prolongated coarse correction; both it
-// and zout are multiplied by K, so they keep the arithmetic type.
+// Post-smoothing: zout = z1 + omega D^-1 ((r - m) - K z1), acc (r - m).zout,
+// with D the vertex's diagonal block of K (formed from the diagonal modes, see
+// OpDiag).  z1 is the pre-smoothed correction plus the prolongated coarse
+// correction; both it and zout are multiplied by K, so they keep the
+// arithmetic type.
 template <typename T, typename V>
 struct OpPostSmooth {
   static constexpr int NACC = 2;
+  static constexpr bool DIAG = true;
   const T* z1;
   const T* r;
-  const T* dinv;
   T* zout;
   const T* q;  // optional: q of the last matvec, for q.zout
   int64_t n;
   const double* scal;
   Partials part;
   int slot0, slot1;
-  double m[3];  // per-case means of r (set by prep)
+  T dd, oo, omega;  // diagonal / off-diagonal entry of K0's diagonal blocks; damping
+  double m[3];      // per-case means of r (set by prep)
   __device__ void prep(int c) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) m[k] = scal[(S_MEAN0 + k) * 8 + c];
@@ -630,13 +715,11 @@ struct OpPostSmooth {
     T u[3];
   };
   struct ERaw {
-    T r[3], d[6], q[3];
+    T r[3], q[3];
   };
   __device__ void efetch(int c, int64_t zoff, uint32_t xy, ERaw& e) const {
 #pragma unroll
     for (int k = 0; k < 3; ++k) e.r[k] = ld(r, (c * 3 + k) * n + zoff, xy);
-#pragma unroll
-    for (int t = 0; t < 6; ++t) e.d[t] = ld(dinv, t * n + zoff, xy);
 #pragma unroll
     for (int k = 0; k < 3; ++k) e.q[k] = q ? ld(q, (c * 3 + k) * n + zoff, xy) : T(0);
   }
@@ -649,15 +732,19 @@ struct OpPostSmooth {
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = (T)w.u[k];
   }
-  __device__ void store(int c, int64_t zoff, uint32_t xy, int, int, int, const T* ku,
-                        const T* uin, const ERaw& e, double& a0, double& a1) const {
+  // The damped block inverse omega D^-1 is formed here from the diagonal modes
+  // dg (cofactors over the determinant), so the pass streams no stored inverse.
+  __device__ void store_diag(int c, int64_t zoff, uint32_t xy, const T* ku, const T* uin,
+                             const ERaw& e, const T (&dg)[4], double& a0, double& a1) const {
+    T d[6];
+    damped_block_inverse(dd, oo, omega, dg, d);
+    const T dxx = d[0], dyy = d[1], dzz = d[2], dxy = d[3], dyz = d[4], dxz = d[5];
     T res[3], rv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       rv[k] = (T)((double)e.r[k] - m[k]);
       res[k] = rv[k] - ku[k];
     }
-    const T dxx = e.d[0], dyy = e.d[1], dzz = e.d[2], dxy = e.d[3], dyz = e.d[4], dxz = e.d[5];
     T zn[3];
     zn[0] = uin[0] + (dxx * res[0] + dxy * res[1] + dxz * res[2]);
     zn[1] = uin[1] + (dxy * res[0] + dyy * res[1] + dyz * res[2]);
@@ -828,45 +915,68 @@ __global__ void simp_kernel(int64_t n, const float* __restrict__ rho, T* __restr
   }
 }
 
-// omega * (sum_a s_{v-a} K0[a,a])^-1, stored as xx, yy, zz, xy, yz, xz planes.
+// Jacobi from a zero start at level 0: z0 = omega D^-1 (r - m) for every active
+// case, with the vertex's diagonal block D formed from the eight element scales
+// around it (OpDiag) instead of read from a stored inverse.  Block b of nb takes
+// grid rows (y, z) b, b + nb, ...; threads run along x.
 template <typename T>
-__global__ void dinv0_kernel(Grid g, const T* __restrict__ s, double dd, double oo, double omega,
-                             T* __restrict__ dinv) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < g.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int gx = (int)(i % g.nx);
-    const int gy = (int)((i / g.nx) % g.ny);
-    const int gz = (int)(i / ((int64_t)g.nx * g.ny));
-    const int xm = gx == 0 ? g.nx - 1 : gx - 1;
-    const int ym = gy == 0 ? g.ny - 1 : gy - 1;
-    const int zm = gz == 0 ? g.nz - 1 : gz - 1;
-    const int64_t nx = g.nx, nxy = (int64_t)g.nx * g.ny;
-    double sum = 0.0, sxy = 0.0, syz = 0.0, sxz = 0.0;
+__device__ __forceinline__ void jacobi0s_rows(const Grid& g, const T* __restrict__ s,
+                                              const BlockDiag0& bd, const T* __restrict__ r,
+                                              T* __restrict__ z, const double* scal,
+                                              const double* mean, int b, int nb) {
+  bool on[NCASE];
+  double m[NCASE][3];
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int64_t e = ((a & 1) ? xm : gx) + nx * ((a & 2) ? ym : gy) + nxy * ((a & 4) ? zm : gz);
-      const double se = (double)s[e];
-      const double sx = (a & 1) ? 1.0 : -1.0, sy = (a & 2) ? 1.0 : -1.0;
-      const double sz = (a & 4) ? 1.0 : -1.0;
-      sum += se;
-      sxy += se * sx * sy;
-      syz += se * sy * sz;
-      sxz += se * sx * sz;
-    }
-    const double a00 = dd * sum, a11 = a00, a22 = a00;
-    const double a01 = oo * sxy, a12 = oo * syz, a02 = oo * sxz;
-    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22;
-    const double c02 = a01 * a12 - a02 * a11, c11 = a00 * a22 - a02 * a02;
-    const double c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
-    const double det = a00 * c00 + a01 * c01 + a02 * c02;
-    const double f = omega / det;
-    dinv[i] = (T)(f * c00);
-    dinv[g.n + i] = (T)(f * c11);
-    dinv[2 * g.n + i] = (T)(f * c22);
-    dinv[3 * g.n + i] = (T)(f * c01);
-    dinv[4 * g.n + i] = (T)(f * c12);
-    dinv[5 * g.n + i] = (T)(f * c02);
+  for (int c = 0; c < NCASE; ++c) {
+    on[c] = scal_active<T>(scal, c);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m[c][k] = mean ? mean[(S_MEAN0 + k) * 8 + c] : 0.0;
   }
+  const T dd = (T)bd.dd, oo = (T)bd.oo, omega = (T)bd.omega;
+  const int64_t n = g.n, nx = g.nx, nxy = (int64_t)g.nx * g.ny;
+  const int rows = g.ny * g.nz;
+  for (int row = b; row < rows; row += nb) {
+    const int y = row % g.ny, zz = row / g.ny;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, zm = zz == 0 ? g.nz - 1 : zz - 1;
+    const T* s_lo_u = s + nxy * zm + nx * ym;  // element rows (y - 1, y) of planes z - 1, z
+    const T* s_lo = s + nxy * zm + nx * y;
+    const T* s_hi_u = s + nxy * zz + nx * ym;
+    const T* s_hi = s + nxy * zz + nx * y;
+    for (int x = threadIdx.x; x < g.nx; x += blockDim.x) {
+      const int xm = x == 0 ? g.nx - 1 : x - 1;
+      T lo[4], hi[4], dg[4], d[6];
+      plane_modes2(s_lo_u[xm] + s_lo_u[x], s_lo_u[xm] - s_lo_u[x], s_lo[xm] + s_lo[x],
+                   s_lo[xm] - s_lo[x], lo);
+      plane_modes2(s_hi_u[xm] + s_hi_u[x], s_hi_u[xm] - s_hi_u[x], s_hi[xm] + s_hi[x],
+                   s_hi[xm] - s_hi[x], hi);
+      vertex_modes(lo, hi, dg);
+      damped_block_inverse(dd, oo, omega, dg, d);
+      const int64_t i = nxy * zz + nx * y + x;
+#pragma unroll
+      for (int c = 0; c < NCASE; ++c) {
+        if (!on[c]) continue;
+        const T r0 = (T)((double)r[(c * 3 + 0) * n + i] - m[c][0]);
+        const T r1 = (T)((double)r[(c * 3 + 1) * n + i] - m[c][1]);
+        const T r2 = (T)((double)r[(c * 3 + 2) * n + i] - m[c][2]);
+        z[(c * 3 + 0) * n + i] = d[0] * r0 + d[3] * r1 + d[5] * r2;
+        z[(c * 3 + 1) * n + i] = d[3] * r0 + d[1] * r1 + d[4] * r2;
+        z[(c * 3 + 2) * n + i] = d[5] * r0 + d[4] * r1 + d[2] * r2;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+jacobi0s_kernel(Grid g, const T* __restrict__ s, BlockDiag0 bd, const T* __restrict__ r,
+                T* __restrict__ z, const double* scal, const double* mean) {
+  jacobi0s_rows<T>(g, s, bd, r, z, scal, mean, blockIdx.x, gridDim.x);
+}
+
+// Batched form: blockIdx.y is the cell.
+__global__ void __launch_bounds__(256) jacobi0s_batched_kernel(const PwBatchCell* __restrict__ cells) {
+  const PwBatchCell& ce = cells[blockIdx.y];
+  jacobi0s_rows<float>(ce.g, ce.s, ce.bd, ce.r, ce.z, ce.scal, ce.scal, blockIdx.x, gridDim.x);
 }
 
 // 27-point stencil of the level-0 operator: thread per (vertex, offset d).
@@ -966,8 +1076,10 @@ Op0BatchPlan* op0_batch_plan(int kind, const Op0BatchCell* cells, int ncells, in
   std::vector<Op0Cell<float, OpPostSmooth<float, float>>> hc;
   for (int c = 0; c < ncells; ++c) {
     const Op0BatchCell& a = cells[c];
-    OpPostSmooth<float, float> op{a.in0, a.in1, a.in2, a.out0, a.in3, a.g.n, a.scal, a.part,
-                                  S_RZNEW, S_QZ, {}};
+    OpPostSmooth<float, float> op{a.in0,   a.in1,  a.out0,          a.in3,
+                                  a.g.n,   a.scal, a.part,          S_RZNEW,
+                                  S_QZ,    (float)a.bd.dd, (float)a.bd.oo, (float)a.bd.omega,
+                                  {}};
     hc.push_back({op, a.g, tile_geom<float>(a.g, a.lz), a.s});
   }
   return build_plan(kind, hc, grid, st);
@@ -1022,9 +1134,10 @@ void op0_residual(const Op0Launch<T>& L, const T* r, const T* z0, V* t, const do
 }
 
 template <typename T, typename V>
-void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const T* dinv, T* zout,
-                     const T* q, const double* scal, Partials part, int* nblk_out) {
-  OpPostSmooth<T, V> op{z1, r, dinv, zout, q, L.g.n, scal, part, S_RZNEW, S_QZ, {}};
+void op0_post_smooth(const Op0Launch<T>& L, const T* z1, const T* r, const BlockDiag0& bd,
+                     T* zout, const T* q, const double* scal, Partials part, int* nblk_out) {
+  OpPostSmooth<T, V> op{z1,      r,      zout,   q,          L.g.n,       scal,
+                        part,    S_RZNEW, S_QZ,  (T)bd.dd,   (T)bd.oo,    (T)bd.omega, {}};
   launch_op0(L, op);
   *nblk_out = tile_geom<T>(L.g).ntiles;
 }
@@ -1053,10 +1166,14 @@ void simp_scale(const Grid& g, const float* rho, T* s, T* keep, double* s64, dou
 }
 
 template <typename T>
-void dinv_level0(const Grid& g, const T* s, double dd, double oo, double omega, T* dinv,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(dinv0_kernel<T>, dim3(pw_blocks(g.n, 256, 8192)), dim3(256), 0, st, g, s, dd,
-                     oo, omega, dinv);
+void jacobi0_level0(const Grid& g, const T* s, const BlockDiag0& bd, const T* r, T* z,
+                    const double* scal, const double* mean, hipStream_t st) {
+  hipLaunchKernelGGL(jacobi0s_kernel<T>, dim3(pw_blocks((int64_t)g.ny * g.nz, 1, 8192)), dim3(256),
+                     0, st, g, s, bd, r, z, scal, mean);
+}
+
+void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(jacobi0s_batched_kernel, dim3(nblk, ncells), dim3(256), 0, st, cells_dev);
 }
 
 template <typename T>
@@ -1069,8 +1186,9 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
   template void op0_matvec_p<T, V>(const Op0Launch<T>&, const V*, const V*, V*, T*,             \
                                    const double*, Partials, int*);                               \
   template void op0_residual<T, V>(const Op0Launch<T>&, const T*, const T*, V*, const double*); \
-  template void op0_post_smooth<T, V>(const Op0Launch<T>&, const T*, const T*, const T*, T*,    \
-                                      const T*, const double*, Partials, int*);
+  template void op0_post_smooth<T, V>(const Op0Launch<T>&, const T*, const T*,                  \
+                                      const BlockDiag0&, T*, const T*, const double*, Partials,   \
+                                      int*);
 #define HMG_INST1(T)                                                                             \
   template void op0_apply<T>(const Op0Launch<T>&, const T*, T*, const double*);                  \
   template void op0_force_residual<T>(const Op0Launch<double>&, const double*,                  \
@@ -1079,7 +1197,8 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
                            int*, hipStream_t);                                                    \
   template void simp_scale<T>(const Grid&, const float*, T*, T*, double*, double*, double,       \
                               double, double, int*, hipStream_t);                                 \
-  template void dinv_level0<T>(const Grid&, const T*, double, double, double, T*, hipStream_t);  \
+  template void jacobi0_level0<T>(const Grid&, const T*, const BlockDiag0&, const T*, T*,         \
+                                  const double*, const double*, hipStream_t);                   \
   template void stencil_level0<T>(const Grid&, const T*, const double*, T*, hipStream_t);
 HMG_INST1(float)
 HMG_INST1(double)

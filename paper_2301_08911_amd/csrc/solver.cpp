@@ -221,7 +221,6 @@ class Solver final : public SolverIface {
     auto A = [&](size_t bytes) { return arena_.alloc(bytes); };
     s_ = (T*)A(sizeof(T) * g0.n);
     rho_ = (T*)A(sizeof(T) * g0.n);
-    dinv0_ = (T*)A(sizeof(T) * 6 * g0.n);
     x_ = (double*)A(sizeof(double) * F);
     if (sizeof(T) == sizeof(double)) {
       s64_ = (double*)s_;
@@ -270,7 +269,7 @@ class Solver final : public SolverIface {
     tplg_ = (double*)A(sizeof(LoadTpl<double>));
     msig_ = (double*)A(sizeof(double) * 8 * 576);
     bad_ = (int*)A(sizeof(int) * 4);
-    for (void* p : {(void*)s_, (void*)rho_, (void*)dinv0_, (void*)x_, (void*)r_, (void*)z_,
+    for (void* p : {(void*)s_, (void*)rho_, (void*)x_, (void*)r_, (void*)z_,
                     (void*)t_, (void*)pa_, (void*)pb_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
                     (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)tplg_,
                     (void*)msig_,
@@ -434,7 +433,6 @@ class Solver final : public SolverIface {
     // Gauss-Seidel needs no damping: level 0 forms its blocks from s on the
     // fly, coarse levels keep the undamped inverses.
     omega_[0] = gs_ ? 1.0 : omega_for(ec_.lam0);
-    if (!gs_) dinv_level0<T>(g0, s_, ec_.dd, ec_.oo, omega_[0], dinv0_, st_);
     for (int l = 1; l < L; ++l) {
       if (l == 1)
         galerkin_first<T, W>(g0, grids_[1], s_, msig4_ ? msig4_ : msig_, lev_[1].st, st_);
@@ -868,8 +866,9 @@ class Solver final : public SolverIface {
       });
       return check_hip("vcycle");
     }
-    clock.timed(HMG_K_JACOBI, vn * (nact * 6 * TB + 6 * TB), st_,
-                [&] { vec_jacobi0<T, T, T>(g0, r0, dinv0_, w0_, scal, scal, st_); });
+    clock.timed(HMG_K_JACOBI, vn * (nact * 6 * TB + TB), st_, [&] {
+      jacobi0_level0<T>(g0, s_, BlockDiag0{ec_.dd, ec_.oo, omega_[0]}, r0, w0_, scal, scal, st_);
+    });
     clock.timed(HMG_K_RESIDUAL, vn * (nact * 3 * (2 * TB + VB) + TB), st_,
                 [&] { op0_residual<T, V>(L0, r0, w0_, t_, scal); });
     restrict_to<V>(g0, grids_[1], t_, lev_[1].r, scal, st_);
@@ -881,8 +880,9 @@ class Solver final : public SolverIface {
       else
         prolong_add<T, V>(g0, grids_[1], w0_, lev_[1].z, scal, false, st_);
     });
-    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 3 * (3 * TB + (qpr ? TB : 0)) + 7 * TB), st_, [&] {
-      op0_post_smooth<T, V>(L0, w0_, r0, dinv0_, zout, qpr, scal, part_, nb);
+    clock.timed(HMG_K_POST_SMOOTH, vn * (nact * 3 * (3 * TB + (qpr ? TB : 0)) + TB), st_, [&] {
+      op0_post_smooth<T, V>(L0, w0_, r0, BlockDiag0{ec_.dd, ec_.oo, omega_[0]}, zout, qpr, scal,
+                            part_, nb);
     });
     return check_hip("vcycle");
   }
@@ -935,7 +935,7 @@ class Solver final : public SolverIface {
   LoadTpl<double> chh64_{};
   LoadTpl<float> chh32_{};
   bool fp16_ready_ = false;  // r_ holds the FP16 cast of the current solution
-  T *s_ = nullptr, *rho_ = nullptr, *dinv0_ = nullptr;
+  T *s_ = nullptr, *rho_ = nullptr;
   double* s64_ = nullptr;    // FP64 copies used by the residual recomputation and C^H
   double* rho64_ = nullptr;
   double* x_ = nullptr;      // iterate kept in FP64
@@ -1035,9 +1035,10 @@ class BatchSolver {
       }
       rs.push_back({g, lz[c], X.s_, X.r_, X.w0_, nullptr, nullptr, X.t_, nullptr, X.scal_,
                     Partials{}});
-      ps.push_back({g, lz[c], X.s_, X.w0_, X.r_, X.dinv0_, nullptr, X.z_, nullptr, X.scal_,
-                    X.part_});
-      jc.push_back({g, nullptr, nullptr, X.r_, nullptr, X.dinv0_, X.w0_, X.scal_, Partials{}});
+      ps.push_back({g, lz[c], X.s_, X.w0_, X.r_, nullptr, nullptr, X.z_, nullptr, X.scal_,
+                    X.part_, {X.ec_.dd, X.ec_.oo, X.omega_[0]}});
+      jc.push_back({g, nullptr, nullptr, X.r_, nullptr, X.s_, X.w0_, X.scal_, Partials{},
+                    {X.ec_.dd, X.ec_.oo, X.omega_[0]}});
     }
     for (int par = 0; par < 2; ++par) {
       mvp_[par] = op0_batch_plan(OP0B_MATVEC, mv[par].data(), B, grid, st_);

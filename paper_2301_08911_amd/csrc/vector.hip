@@ -183,11 +183,6 @@ __global__ void __launch_bounds__(VB) jacobi0_kernel(Grid g, const R* __restrict
   jacobi0_body<R, D, Z>(g, r, dinv, z, scal, mean);
 }
 
-__global__ void __launch_bounds__(VB) jacobi0_batched_kernel(const PwBatchCell* __restrict__ cells) {
-  const PwBatchCell& ce = cells[blockIdx.y];
-  jacobi0_body<float, float, float>(ce.g, ce.r, ce.dinv, ce.z, ce.scal, ce.scal);
-}
-
 template <typename T>
 __global__ void fill_kernel(T* __restrict__ a, int64_t count, T v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -425,9 +420,6 @@ int vec_blocks(const Grid& g) { return blocks_for(g.n); }
 
 void update_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(update_batched_kernel, dim3(nblk, ncells * NCASE), dim3(VB), 0, st, cells_dev);
-}
-void jacobi0_batched(const PwBatchCell* cells_dev, int ncells, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(jacobi0_batched_kernel, dim3(nblk, ncells), dim3(VB), 0, st, cells_dev);
 }
 int vec_blocks_for(int64_t n) { return blocks_for(n); }
 
