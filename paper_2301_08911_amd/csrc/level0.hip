@@ -232,7 +232,9 @@ template <class Op>
 struct OpDiag<Op, std::void_t<decltype(Op::DIAG)>> : std::bool_constant<Op::DIAG> {};
 
 // omega (dd S I + oo M)^-1 for the modes dg = {S, M_xy, M_yz, M_xz} (OpDiag),
-// by cofactors over the determinant, as d = {xx, yy, zz, xy, yz, xz}.
+// by cofactors over the determinant, as d = {xx, yy, zz, xy, yz, xz}.  In FP32
+// the determinant is inverted by the hardware reciprocal (1 ulp), which a
+// smoother tolerates; FP64 divides.
 template <typename T>
 __device__ __forceinline__ void damped_block_inverse(T dd, T oo, T omega, const T (&dg)[4],
                                                      T (&d)[6]) {
@@ -240,7 +242,12 @@ __device__ __forceinline__ void damped_block_inverse(T dd, T oo, T omega, const 
   const T d01 = oo * dg[1], d12 = oo * dg[2], d02 = oo * dg[3];
   const T c00 = d0 * d0 - d12 * d12, c11 = d0 * d0 - d02 * d02, c22 = d0 * d0 - d01 * d01;
   const T c01 = d02 * d12 - d01 * d0, c12 = d01 * d02 - d0 * d12, c02 = d01 * d12 - d02 * d0;
-  const T f = omega / (d0 * c00 + d01 * c01 + d02 * c02);
+  const T det = d0 * c00 + d01 * c01 + d02 * c02;
+  T f;
+  if constexpr (sizeof(T) == 4)
+    f = omega * __builtin_amdgcn_rcpf(det);
+  else
+    f = omega / det;
   d[0] = f * c00;
   d[1] = f * c11;
   d[2] = f * c22;
