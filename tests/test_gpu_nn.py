@@ -221,7 +221,8 @@ def test_trained_network_gain_on_held_out_cells():
         pred = net.forward(inp[None].contiguous())[0]
         errs.append(float(((pred - tgt) ** 2).mean() / (tgt ** 2).mean()))
     print("relative MSE on held-out 32^3 cells", errs, flush=True)
-    assert np.mean(errs) < 0.95, errs
+    # the 2000-cell network: 0.44-0.59 on these cells (predicting zero gives 1)
+    assert np.mean(errs) < 0.7, errs
     x, _ = TW.make_cell(64, 990100)
     ctx = Context((64, 64, 64), precision="fp32")
     rho = ctx.filter(dev(x), radius=2.0)
@@ -234,8 +235,9 @@ def test_trained_network_gain_on_held_out_cells():
     print("guess relres", rr, "used", used, "iters", res.iters.tolist(), "cold", res0.iters.tolist(),
           flush=True)
     assert res.converged and res0.converged
-    if not used:
-        assert (res.iters == res0.iters).all()
+    # the energy-scaled guess of this cell passes the acceptance test (relres
+    # 0.43 after its correction cycle)
+    assert used and rr <= 0.5, rr
     C, C0 = ctx.elastic_tensor(), cold.elastic_tensor()
     assert np.linalg.norm(C - C0) / np.linalg.norm(C0) < 1e-5
 
