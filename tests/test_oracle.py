@@ -119,6 +119,35 @@ def test_csr_equals_elementwise_and_kills_translations(K0):
     assert abs(K - K.T).max() < 1e-15
 
 
+def test_vertex_diagonal_block_from_eight_scales(K0):
+    """The level-0 smoothers form each vertex's 3x3 diagonal block of K (Sec. 4.2,
+    Eq. st-assemb) from the eight element scales around it: dd * sum_e s_e on the
+    diagonal and oo * sum_e s_e t_i t_j off it, with t_i = +1 when element e lies on
+    the low side of the vertex along axis i and -1 otherwise, dd and oo the diagonal
+    and off-diagonal entries of corner 0's block of K0.  This holds because K0's
+    corner blocks differ only by the reflections that map the corners onto each
+    other; checked here against the assembled operator."""
+    shape = (5, 4, 6)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(17)
+    s = 10.0 ** rng.uniform(-9, 0, nx * ny * nz)
+    K = O.assemble_stiffness(s, shape, K0).tocsr()
+    dd, oo = K0[0, 0], K0[0, 1]
+    assert abs(oo) > 1e-3 * abs(dd)  # the off-diagonal pattern is not vacuous
+    for v in range(nx * ny * nz):
+        x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+        S, M = 0.0, np.zeros((3, 3))
+        for dz, dy, dx in itertools.product((-1, 0), repeat=3):
+            e = (x + dx) % nx + nx * (((y + dy) % ny) + ny * ((z + dz) % nz))
+            t = np.array([1.0 if d == -1 else -1.0 for d in (dx, dy, dz)])
+            S += s[e]
+            M += s[e] * np.outer(t, t)
+        ref = oo * M
+        np.fill_diagonal(ref, dd * S)
+        blk = K[3 * v:3 * v + 3, 3 * v:3 * v + 3].toarray()
+        assert np.abs(blk - ref).max() <= 1e-13 * abs(dd) * S, (v, blk, ref)
+
+
 def test_operator_at_sampled_vertices_equals_csr(K0):
     """The per-vertex operator (used for sampled checks of full-size grids)
     agrees with the assembled periodic CSR matrix, seam vertices included."""
