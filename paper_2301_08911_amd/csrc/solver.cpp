@@ -234,6 +234,7 @@ class Solver final : public SolverIface {
     t_ = (V*)A(sizeof(V) * F);
     pa_ = (T*)A(sizeof(T) * F);
     pb_ = (T*)A(sizeof(T) * F);
+    pc_ = (T*)A(sizeof(T) * F);
     q_ = (T*)A(sizeof(T) * F);
     // The plain forms reuse q (dead while the V-cycle runs); the reduced-
     // precision form keeps q for the Polak-Ribiere beta.
@@ -270,7 +271,7 @@ class Solver final : public SolverIface {
     msig_ = (double*)A(sizeof(double) * 8 * 576);
     bad_ = (int*)A(sizeof(int) * 4);
     for (void* p : {(void*)s_, (void*)rho_, (void*)x_, (void*)r_, (void*)z_,
-                    (void*)t_, (void*)pa_, (void*)pb_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
+                    (void*)t_, (void*)pa_, (void*)pb_, (void*)pc_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
                     (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)tplg_,
                     (void*)msig_,
                     (void*)bad_, (void*)s64_, (void*)rho64_})
@@ -513,8 +514,10 @@ class Solver final : public SolverIface {
       it_count[c] = 0;
       if (hscal_[S_TRIVIAL * 8 + c] != 0.0) vec_fill<double>(x_ + c * cs, cs, 0.0, st_);
     }
-    T* pold = pa_;
-    T* pnew = pb_;
+    // Directions rotate through three buffers: buf[ib] holds the newest one
+    // (the matvec's p_old), buf[ib + 2] the one before it.
+    T* buf[3] = {pa_, pb_, pc_};
+    int ib = 0;
     active_count_ = count(active);
     if (any(active)) {
       HMG_TRY(vcycle_apply(r_, z_, nullptr, scal_, &nb));
@@ -523,30 +526,47 @@ class Solver final : public SolverIface {
                            hipMemcpyDeviceToDevice, st_);
     }
     int it = 0;
-    bool pending = false;  // x += alpha p of the newest direction (pold after the swap) is owed
+    // Directions whose x += alpha p is still owed: 0, 1 (buf[ib], S_XALPHA) or 2
+    // (and buf[ib + 2], S_XALPHA2).
+    int npend = 0;
+    auto flush = [&]() {
+      if (npend > 0)
+        vec_flush_x<T>(g0, x_, npend == 2 ? buf[(ib + 2) % 3] : nullptr, buf[ib], scal_, st_);
+      npend = 0;
+    };
     while (any(active) && it < max_iter) {
       ++it;
       const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T), VB = sizeof(V);
+      T* pold = buf[ib];
+      T* pnew = buf[(ib + 1) % 3];  // held p_{k-3}, whose x term is no longer owed
       clock.timed(HMG_K_MATVEC, vn * (nact * 12 * TB + TB), st_, [&] {
         op0_matvec_p<T, T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
       });
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      // x advances every other iteration, by alpha_{k-1} p_{k-1} + alpha_k p_k
-      // (both directions are still in the two p buffers): a quarter less
-      // traffic in the update pass.  A recomputation of f - K x and the end of
-      // the solve first flush a pending alpha_k p_k.
-      const bool defer = !pending;
-      clock.timed(HMG_K_UPDATE, vn * nact * (defer ? 9 * TB : 48 + 15 * TB), st_, [&] {
-        vec_update_r2<T>(g0, x_, defer ? nullptr : pold, pnew, r_, q_, scal_, part_, &nb, st_);
+      // x advances every third iteration, by alpha_{k-2} p_{k-2} +
+      // alpha_{k-1} p_{k-1} + alpha_k p_k (all three directions are still in
+      // the p buffers): a third less traffic in the update pass than advancing
+      // it every iteration.  A recomputation of f - K x and the end of the
+      // solve first flush the pending terms.
+      const bool defer = npend < 2;
+      clock.timed(HMG_K_UPDATE, vn * nact * (defer ? 9 * TB : 48 + 18 * TB), st_, [&] {
+        vec_update_r3<T>(g0, x_, defer ? nullptr : buf[(ib + 2) % 3], defer ? nullptr : pold,
+                         pnew, r_, q_, scal_, part_, &nb, st_);
       });
-      if (defer)
+      if (defer) {
+        if (npend == 1)
+          (void)hipMemcpyAsync(scal_ + S_XALPHA2 * 8, scal_ + S_XALPHA * 8, sizeof(double) * 8,
+                               hipMemcpyDeviceToDevice, st_);
         (void)hipMemcpyAsync(scal_ + S_XALPHA * 8, scal_ + S_ALPHA * 8, sizeof(double) * 8,
                              hipMemcpyDeviceToDevice, st_);
-      pending = defer;
+        ++npend;
+      } else {
+        npend = 0;
+      }
       fin_sum(part_, S_RR, nb, scal_, false, st_);
       fin_mean(part_, nb, g0.n, scal_, st_);
-      std::swap(pold, pnew);
+      ib = (ib + 1) % 3;
       for (int c = 0; c < NCASE; ++c) it_count[c] += active[c] ? 1 : 0;
       HMG_TRY(read_scal(scal_, hscal_));
       bool check[NCASE], event[NCASE];
@@ -571,10 +591,7 @@ class Solver final : public SolverIface {
         // stops; the recomputed residual also replaces the recursive one (it
         // is written over r of the checked cases: a case that stops no longer
         // needs r).
-        if (pending) {
-          vec_flush_x<T>(g0, x_, pold, scal_, st_);
-          pending = false;
-        }
+        flush();
         set_mask(aux_, check);
         clock.timed(HMG_K_TRUE_RESIDUAL, (double)g0.n * (count(check) * (24 + 3 * sizeof(T)) + 8),
                     st_, [&] { op0_force_residual<T>(L64, tplg_, x_, r_, aux_, part_, &nb); });
@@ -604,7 +621,7 @@ class Solver final : public SolverIface {
       if (kPR) fin_sum(part_, S_QZ, nb, scal_, false, st_);
       fin_beta(scal_, kPR, st_);
     }
-    if (pending) vec_flush_x<T>(g0, x_, pold, scal_, st_);
+    flush();
     // Zero-mean solution, recomputed final residuals.
     vec_mean_partial<double>(g0, x_, part_, &nb, st_);
     fin_mean(part_, nb, g0.n, aux_, st_);
@@ -942,7 +959,7 @@ class Solver final : public SolverIface {
   T* r_ = nullptr;  // level-0 residual (arithmetic type)
   T* z_ = nullptr;  // preconditioned residual
   V* t_ = nullptr;  // V-cycle work: level-0 residual after pre-smoothing
-  T *pa_ = nullptr, *pb_ = nullptr;
+  T *pa_ = nullptr, *pb_ = nullptr, *pc_ = nullptr;
   T* q_ = nullptr;   // q = K p
   T* w0_ = nullptr;  // V-cycle level-0 correction (the plain forms alias q_)
   T* zc_ = nullptr;  // coarsest-level correction

@@ -59,15 +59,17 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
 }
 
 // r -= alpha q for load case c, with partials of ||r||^2 and of sum r per
-// component.  The single-cell solver advances the iterate every other
-// iteration: the two direction buffers of the matvec still hold p_{k-1} and
-// p_k, so XMODE 1 adds alpha_{k-1} p_{k-1} + alpha_k p_k and XMODE 0 leaves x
-// alone (36 and 12 bytes per DOF instead of 32 and 32); XMODE 2 is the plain
-// x += alpha_k p_k of the batched solver.  One load case per block row: a
-// thread streams the three components of one case, which keeps its registers
-// (and the number of concurrent streams per wave) small.
+// component.  The single-cell solver advances the iterate every third
+// iteration: the three direction buffers of the matvec still hold p_{k-2},
+// p_{k-1} and p_k, so XMODE 3 adds alpha_{k-2} p_{k-2} + alpha_{k-1} p_{k-1} +
+// alpha_k p_k and XMODE 0 leaves x alone (40 and 12 bytes per DOF instead of 32
+// and 32); XMODE 1 folds two directions, XMODE 2 is the plain x += alpha_k p_k
+// of the batched solver.  One load case per block row: a thread streams the
+// three components of one case, which keeps its registers (and the number of
+// concurrent streams per wave) small.
 template <typename T, int XMODE>
 __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ x,
+                                            const T* __restrict__ pp2,
                                             const T* __restrict__ pprev, const T* __restrict__ p,
                                             T* __restrict__ r, const T* __restrict__ q,
                                             const double* scal, const Partials& part, int c) {
@@ -82,7 +84,8 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
     return;
   }
   const double al64 = scal[S_ALPHA * 8 + c];
-  const double xa64 = XMODE == 1 ? scal[S_XALPHA * 8 + c] : 0.0;
+  const double xa64 = XMODE == 1 || XMODE == 3 ? scal[S_XALPHA * 8 + c] : 0.0;
+  const double xb64 = XMODE == 3 ? scal[S_XALPHA2 * 8 + c] : 0.0;
   const T al = (T)al64;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // ||r||^2, sum r per component
   const int64_t n = g.n;
@@ -93,6 +96,8 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
     for (int k = 0; k < 3; ++k) {
       const int64_t o = base + (int64_t)k * n + i;
       if (XMODE == 1) x[o] += xa64 * (double)pprev[o] + al64 * (double)p[o];
+      if (XMODE == 3)
+        x[o] += (xb64 * (double)pp2[o] + xa64 * (double)pprev[o]) + al64 * (double)p[o];
       if (XMODE == 2) x[o] += al64 * (double)p[o];
       const T rv = r[o] - al * q[o];
       r[o] = rv;
@@ -111,20 +116,24 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
 
 template <typename T, int XMODE>
 __global__ void __launch_bounds__(VB) update2_kernel(Grid g, double* __restrict__ x,
+                                                     const T* __restrict__ pp2,
                                                      const T* __restrict__ pprev,
                                                      const T* __restrict__ p, T* __restrict__ r,
                                                      const T* __restrict__ q, const double* scal,
                                                      Partials part) {
-  update_case<T, XMODE>(g, x, pprev, p, r, q, scal, part, blockIdx.y);
+  update_case<T, XMODE>(g, x, pp2, pprev, p, r, q, scal, part, blockIdx.y);
 }
 
-// x += S_XALPHA p for the active cases (one case per blockIdx.y).
-template <typename T>
+// x += [S_XALPHA2 pp2 +] S_XALPHA p for the active cases (one case per
+// blockIdx.y): the directions still owed to the iterate.
+template <typename T, bool TWO>
 __global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict__ x,
+                                                     const T* __restrict__ pp2,
                                                      const T* __restrict__ p, const double* scal) {
   const int c = blockIdx.y;
   if (!case_on(scal, c)) return;
   const double xa = scal[S_XALPHA * 8 + c];
+  const double xb = TWO ? scal[S_XALPHA2 * 8 + c] : 0.0;
   const int64_t n = g.n;
   const int64_t base = (int64_t)c * 3 * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -132,14 +141,17 @@ __global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict_
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t o = base + (int64_t)k * n + i;
-      x[o] += xa * (double)p[o];
+      if (TWO)
+        x[o] += xb * (double)pp2[o] + xa * (double)p[o];
+      else
+        x[o] += xa * (double)p[o];
     }
 }
 
 __global__ void __launch_bounds__(VB) update_batched_kernel(const PwBatchCell* __restrict__ cells) {
   // blockIdx.y = cell * NCASE + load case; x += alpha p every iteration
   const PwBatchCell& ce = cells[blockIdx.y / NCASE];
-  update_case<float, 2>(ce.g, ce.x, nullptr, ce.p, ce.r, ce.q, ce.scal, ce.part,
+  update_case<float, 2>(ce.g, ce.x, nullptr, nullptr, ce.p, ce.r, ce.q, ce.scal, ce.part,
                         blockIdx.y % NCASE);
 }
 
@@ -438,29 +450,40 @@ template void vec_convert<bf16, double>(double*, const bf16*, int64_t, hipStream
 template void vec_convert<double, f16>(f16*, const double*, int64_t, hipStream_t);
 
 template <typename T>
-void vec_update_r2(const Grid& g, double* x, const T* pprev, const T* p, T* r, const T* q,
-                   const double* scal, Partials part, int* nblk_out, hipStream_t st) {
+void vec_update_r3(const Grid& g, double* x, const T* pp2, const T* pprev, const T* p, T* r,
+                   const T* q, const double* scal, Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  if (pprev)
-    hipLaunchKernelGGL((update2_kernel<T, 1>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pprev, p,
-                       r, q, scal, part);
+  if (pprev && pp2)
+    hipLaunchKernelGGL((update2_kernel<T, 3>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
+                       p, r, q, scal, part);
+  else if (pprev)
+    hipLaunchKernelGGL((update2_kernel<T, 1>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
+                       p, r, q, scal, part);
   else
-    hipLaunchKernelGGL((update2_kernel<T, 0>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pprev, p,
-                       r, q, scal, part);
+    hipLaunchKernelGGL((update2_kernel<T, 0>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
+                       p, r, q, scal, part);
   *nblk_out = nb;
 }
 template <typename T>
-void vec_flush_x(const Grid& g, double* x, const T* p, const double* scal, hipStream_t st) {
-  hipLaunchKernelGGL((flush_x_kernel<T>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st, g, x, p,
-                     scal);
+void vec_flush_x(const Grid& g, double* x, const T* pp2, const T* p, const double* scal,
+                 hipStream_t st) {
+  if (pp2)
+    hipLaunchKernelGGL((flush_x_kernel<T, true>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st, g,
+                       x, pp2, p, scal);
+  else
+    hipLaunchKernelGGL((flush_x_kernel<T, false>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st,
+                       g, x, pp2, p, scal);
 }
-template void vec_update_r2<float>(const Grid&, double*, const float*, const float*, float*,
-                                   const float*, const double*, Partials, int*, hipStream_t);
-template void vec_update_r2<double>(const Grid&, double*, const double*, const double*, double*,
-                                    const double*, const double*, Partials, int*, hipStream_t);
-template void vec_flush_x<float>(const Grid&, double*, const float*, const double*, hipStream_t);
+template void vec_update_r3<float>(const Grid&, double*, const float*, const float*, const float*,
+                                   float*, const float*, const double*, Partials, int*,
+                                   hipStream_t);
+template void vec_update_r3<double>(const Grid&, double*, const double*, const double*,
+                                    const double*, double*, const double*, const double*, Partials,
+                                    int*, hipStream_t);
+template void vec_flush_x<float>(const Grid&, double*, const float*, const float*, const double*,
+                                 hipStream_t);
 template void vec_flush_x<double>(const Grid&, double*, const double*, const double*,
-                                  hipStream_t);
+                                  const double*, hipStream_t);
 
 template <typename R, typename D, typename Z>
 void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,
