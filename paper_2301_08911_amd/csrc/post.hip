@@ -269,7 +269,12 @@ __global__ void __launch_bounds__(256) oc_step_kernel(Partials part, int nblk, i
       state[0] = mid;
     else
       state[1] = mid;
-    if (state[1] - state[0] < 1e-15) state[2] = 1.0;
+    // Once the next midpoint rounds to an end of the bracket, every further
+    // step leaves lambda = exp(next) (the bracket stays or collapses onto that
+    // end), so the search stops there with the same lambda; for |log lambda|
+    // above ~8 the width test alone never fires (adjacent doubles are wider).
+    const double next = 0.5 * (state[0] + state[1]);
+    if (state[1] - state[0] < 1e-15 || next == state[0] || next == state[1]) state[2] = 1.0;
     state[3] = exp(0.5 * (state[0] + state[1]));
   }
 }
