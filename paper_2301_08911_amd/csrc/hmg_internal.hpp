@@ -120,8 +120,9 @@ enum Slot {
   S_RESTART,    // 1: the residual was just recomputed; restart the direction (beta = 0)
   S_QZ,         // q.z_new (Polak-Ribiere form of beta)
   S_REPLACED,   // 1: r was replaced by f - K x this iteration (beta falls back to r.z ratios)
-  S_XALPHA,     // alpha of the newest direction whose x += alpha p is still pending
-  S_XALPHA2,    // alpha of the older of two pending directions
+  S_XALPHA,     // alphas of the directions whose x += alpha p is still pending:
+  S_XALPHA2,    // S_XALPHA + j for the (j+1)-th newest (consecutive slots)
+  S_XALPHA3,
   S_NSLOT
 };
 
@@ -215,18 +216,19 @@ void stencil_level0(const Grid& g, const T* s, const double* K0_dev, T* st, hipS
 // ---------------------------------------------------------------- vectors
 // x += alpha p (FP64 iterate), r -= alpha q; partials ||r||^2 (S_RR) and
 // sum r (S_MEAN*).
-// r -= alpha q (S_ALPHA) with the FP64 iterate advanced every third iteration:
-// pprev == nullptr leaves x alone (alpha p becomes pending; the caller moves
-// S_XALPHA to S_XALPHA2 and S_ALPHA to S_XALPHA), otherwise
-// x += [S_XALPHA2 pp2 +] S_XALPHA pprev + S_ALPHA p (pp2 may be nullptr).
-// Partials per block of ||r||^2 (slot S_RR) and of sum r per component (S_MEAN*).
+// r -= alpha q (S_ALPHA) with the FP64 iterate advanced every fourth iteration:
+// npend = 0 leaves x alone (alpha p becomes pending; the caller shifts the
+// pending alphas up one slot and moves S_ALPHA to S_XALPHA), otherwise
+// x += sum_{j < npend} S_XALPHA+j pend[j] + S_ALPHA p, pend[j] the (j+1)-th
+// newest pending direction (npend <= 3).  Partials per block of ||r||^2 (slot
+// S_RR) and of sum r per component (S_MEAN*).
 template <typename T>
-void vec_update_r3(const Grid& g, double* x, const T* pp2, const T* pprev, const T* p, T* r,
+void vec_update_r4(const Grid& g, double* x, const T* const* pend, int npend, const T* p, T* r,
                    const T* q, const double* scal, Partials part, int* nblk_out, hipStream_t st);
-// x += [S_XALPHA2 pp2 +] S_XALPHA p for the cases active in scal (the pending
-// directions; pp2 may be nullptr).
+// x += sum_{j < npend} S_XALPHA+j pend[j] for the cases active in scal (the
+// pending directions, 1 <= npend <= 3; npend = 0 does nothing).
 template <typename T>
-void vec_flush_x(const Grid& g, double* x, const T* pp2, const T* p, const double* scal,
+void vec_flush_x(const Grid& g, double* x, const T* const* pend, int npend, const double* scal,
                  hipStream_t st);
 template <typename S, typename D>
 void vec_convert(D* dst, const S* src, int64_t count, hipStream_t st);

@@ -235,6 +235,7 @@ class Solver final : public SolverIface {
     pa_ = (T*)A(sizeof(T) * F);
     pb_ = (T*)A(sizeof(T) * F);
     pc_ = (T*)A(sizeof(T) * F);
+    pd_ = (T*)A(sizeof(T) * F);
     q_ = (T*)A(sizeof(T) * F);
     // The plain forms reuse q (dead while the V-cycle runs); the reduced-
     // precision form keeps q for the Polak-Ribiere beta.
@@ -271,7 +272,7 @@ class Solver final : public SolverIface {
     msig_ = (double*)A(sizeof(double) * 8 * 576);
     bad_ = (int*)A(sizeof(int) * 4);
     for (void* p : {(void*)s_, (void*)rho_, (void*)x_, (void*)r_, (void*)z_,
-                    (void*)t_, (void*)pa_, (void*)pb_, (void*)pc_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
+                    (void*)t_, (void*)pa_, (void*)pb_, (void*)pc_, (void*)pd_, (void*)q_, (void*)Ainv_, (void*)part_.buf,
                     (void*)scal_, (void*)aux_, (void*)misc_, (void*)K0dev_, (void*)tplg_,
                     (void*)msig_,
                     (void*)bad_, (void*)s64_, (void*)rho64_})
@@ -514,9 +515,10 @@ class Solver final : public SolverIface {
       it_count[c] = 0;
       if (hscal_[S_TRIVIAL * 8 + c] != 0.0) vec_fill<double>(x_ + c * cs, cs, 0.0, st_);
     }
-    // Directions rotate through three buffers: buf[ib] holds the newest one
-    // (the matvec's p_old), buf[ib + 2] the one before it.
-    T* buf[3] = {pa_, pb_, pc_};
+    // Directions rotate through NB buffers: buf[ib] holds the newest one (the
+    // matvec's p_old), buf[ib - j] the (j+1)-th newest.
+    constexpr int NB = 4;
+    T* buf[NB] = {pa_, pb_, pc_, pd_};
     int ib = 0;
     active_count_ = count(active);
     if (any(active)) {
@@ -526,38 +528,46 @@ class Solver final : public SolverIface {
                            hipMemcpyDeviceToDevice, st_);
     }
     int it = 0;
-    // Directions whose x += alpha p is still owed: 0, 1 (buf[ib], S_XALPHA) or 2
-    // (and buf[ib + 2], S_XALPHA2).
+    // Directions whose x += alpha p is still owed: the npend newest ones,
+    // buf[ib - j] with its alpha in slot S_XALPHA + j (npend <= NB - 1).
     int npend = 0;
+    auto pending_dirs = [&](const T** pend) {
+      for (int j = 0; j < npend; ++j) pend[j] = buf[(ib - j + NB) % NB];
+    };
     auto flush = [&]() {
-      if (npend > 0)
-        vec_flush_x<T>(g0, x_, npend == 2 ? buf[(ib + 2) % 3] : nullptr, buf[ib], scal_, st_);
+      if (npend > 0) {
+        const T* pend[NB - 1];
+        pending_dirs(pend);
+        vec_flush_x<T>(g0, x_, pend, npend, scal_, st_);
+      }
       npend = 0;
     };
     while (any(active) && it < max_iter) {
       ++it;
       const double nact = (double)count(active), vn = (double)g0.n, TB = sizeof(T), VB = sizeof(V);
       T* pold = buf[ib];
-      T* pnew = buf[(ib + 1) % 3];  // held p_{k-3}, whose x term is no longer owed
+      T* pnew = buf[(ib + 1) % NB];  // held p_{k-NB}, whose x term is no longer owed
       clock.timed(HMG_K_MATVEC, vn * (nact * 12 * TB + TB), st_, [&] {
         op0_matvec_p<T, T>(L0, z_, pold, pnew, q_, scal_, part_, &nb);
       });
       fin_sum(part_, S_PQ, nb, scal_, false, st_);
       fin_alpha(scal_, st_);
-      // x advances every third iteration, by alpha_{k-2} p_{k-2} +
-      // alpha_{k-1} p_{k-1} + alpha_k p_k (all three directions are still in
-      // the p buffers): a third less traffic in the update pass than advancing
-      // it every iteration.  A recomputation of f - K x and the end of the
-      // solve first flush the pending terms.
-      const bool defer = npend < 2;
-      clock.timed(HMG_K_UPDATE, vn * nact * (defer ? 9 * TB : 48 + 18 * TB), st_, [&] {
-        vec_update_r3<T>(g0, x_, defer ? nullptr : buf[(ib + 2) % 3], defer ? nullptr : pold,
-                         pnew, r_, q_, scal_, part_, &nb, st_);
+      // x advances every NB-th iteration, by alpha_{k-NB+1} p_{k-NB+1} + .. +
+      // alpha_k p_k (all NB directions are still in the p buffers): the update
+      // pass moves 60 B per vertex and case on average instead of 96 for
+      // advancing x every iteration.  A recomputation of f - K x and the end of
+      // the solve first flush the pending terms.
+      const bool defer = npend < NB - 1;
+      clock.timed(HMG_K_UPDATE, vn * nact * (defer ? 9 * TB : 48 + 3 * (NB + 3) * TB), st_, [&] {
+        const T* pend[NB - 1];
+        pending_dirs(pend);
+        vec_update_r4<T>(g0, x_, pend, defer ? 0 : npend, pnew, r_, q_, scal_, part_, &nb, st_);
       });
       if (defer) {
-        if (npend == 1)
-          (void)hipMemcpyAsync(scal_ + S_XALPHA2 * 8, scal_ + S_XALPHA * 8, sizeof(double) * 8,
-                               hipMemcpyDeviceToDevice, st_);
+        // shift the pending alphas one slot older, then the new one into S_XALPHA
+        for (int j = npend; j > 0; --j)
+          (void)hipMemcpyAsync(scal_ + (S_XALPHA + j) * 8, scal_ + (S_XALPHA + j - 1) * 8,
+                               sizeof(double) * 8, hipMemcpyDeviceToDevice, st_);
         (void)hipMemcpyAsync(scal_ + S_XALPHA * 8, scal_ + S_ALPHA * 8, sizeof(double) * 8,
                              hipMemcpyDeviceToDevice, st_);
         ++npend;
@@ -566,7 +576,7 @@ class Solver final : public SolverIface {
       }
       fin_sum(part_, S_RR, nb, scal_, false, st_);
       fin_mean(part_, nb, g0.n, scal_, st_);
-      ib = (ib + 1) % 3;
+      ib = (ib + 1) % NB;
       for (int c = 0; c < NCASE; ++c) it_count[c] += active[c] ? 1 : 0;
       HMG_TRY(read_scal(scal_, hscal_));
       bool check[NCASE], event[NCASE];
@@ -959,7 +969,7 @@ class Solver final : public SolverIface {
   T* r_ = nullptr;  // level-0 residual (arithmetic type)
   T* z_ = nullptr;  // preconditioned residual
   V* t_ = nullptr;  // V-cycle work: level-0 residual after pre-smoothing
-  T *pa_ = nullptr, *pb_ = nullptr, *pc_ = nullptr;
+  T *pa_ = nullptr, *pb_ = nullptr, *pc_ = nullptr, *pd_ = nullptr;
   T* q_ = nullptr;   // q = K p
   T* w0_ = nullptr;  // V-cycle level-0 correction (the plain forms alias q_)
   T* zc_ = nullptr;  // coarsest-level correction

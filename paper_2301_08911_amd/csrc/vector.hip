@@ -59,18 +59,22 @@ __device__ __forceinline__ void block_sum_multi(double (&v)[NV], double* lds /* 
 }
 
 // r -= alpha q for load case c, with partials of ||r||^2 and of sum r per
-// component.  The single-cell solver advances the iterate every third
-// iteration: the three direction buffers of the matvec still hold p_{k-2},
-// p_{k-1} and p_k, so XMODE 3 adds alpha_{k-2} p_{k-2} + alpha_{k-1} p_{k-1} +
-// alpha_k p_k and XMODE 0 leaves x alone (40 and 12 bytes per DOF instead of 32
-// and 32); XMODE 1 folds two directions, XMODE 2 is the plain x += alpha_k p_k
-// of the batched solver.  One load case per block row: a thread streams the
-// three components of one case, which keeps its registers (and the number of
-// concurrent streams per wave) small.
+// component.  The single-cell solver advances the iterate every fourth
+// iteration: the four direction buffers of the matvec still hold p_{k-3} ..
+// p_k, so XMODE 4 adds alpha_{k-3} p_{k-3} + .. + alpha_k p_k and XMODE 0
+// leaves x alone (44 and 12 bytes per DOF instead of 32 and 32); XMODE 1 and
+// 3 fold two and three directions, XMODE 2 is the plain x += alpha_k p_k of
+// the batched solver.  pend[j] is the (j+1)-th newest pending direction, with
+// its alpha in slot S_XALPHA + j.  One load case per block row: a thread
+// streams the three components of one case, which keeps its registers (and the
+// number of concurrent streams per wave) small.
+template <typename T>
+struct Pending {
+  const T* d[3];
+};
 template <typename T, int XMODE>
 __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ x,
-                                            const T* __restrict__ pp2,
-                                            const T* __restrict__ pprev, const T* __restrict__ p,
+                                            const Pending<T> pend, const T* __restrict__ p,
                                             T* __restrict__ r, const T* __restrict__ q,
                                             const double* scal, const Partials& part, int c) {
   __shared__ double red[(VB / 64) * 4];
@@ -84,8 +88,10 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
     return;
   }
   const double al64 = scal[S_ALPHA * 8 + c];
-  const double xa64 = XMODE == 1 || XMODE == 3 ? scal[S_XALPHA * 8 + c] : 0.0;
-  const double xb64 = XMODE == 3 ? scal[S_XALPHA2 * 8 + c] : 0.0;
+  constexpr int NP = XMODE == 1 ? 1 : (XMODE == 3 ? 2 : (XMODE == 4 ? 3 : 0));  // pending folded
+  double xa[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < NP; ++j) xa[j] = scal[(S_XALPHA + j) * 8 + c];
   const T al = (T)al64;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};  // ||r||^2, sum r per component
   const int64_t n = g.n;
@@ -95,9 +101,13 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t o = base + (int64_t)k * n + i;
-      if (XMODE == 1) x[o] += xa64 * (double)pprev[o] + al64 * (double)p[o];
-      if (XMODE == 3)
-        x[o] += (xb64 * (double)pp2[o] + xa64 * (double)pprev[o]) + al64 * (double)p[o];
+      if constexpr (NP > 0) {
+        // oldest direction first
+        double dx = xa[NP - 1] * (double)pend.d[NP - 1][o];
+#pragma unroll
+        for (int j = NP - 2; j >= 0; --j) dx += xa[j] * (double)pend.d[j][o];
+        x[o] += dx + al64 * (double)p[o];
+      }
       if (XMODE == 2) x[o] += al64 * (double)p[o];
       const T rv = r[o] - al * q[o];
       r[o] = rv;
@@ -116,24 +126,23 @@ __device__ __forceinline__ void update_case(const Grid& g, double* __restrict__ 
 
 template <typename T, int XMODE>
 __global__ void __launch_bounds__(VB) update2_kernel(Grid g, double* __restrict__ x,
-                                                     const T* __restrict__ pp2,
-                                                     const T* __restrict__ pprev,
+                                                     const Pending<T> pend,
                                                      const T* __restrict__ p, T* __restrict__ r,
                                                      const T* __restrict__ q, const double* scal,
                                                      Partials part) {
-  update_case<T, XMODE>(g, x, pp2, pprev, p, r, q, scal, part, blockIdx.y);
+  update_case<T, XMODE>(g, x, pend, p, r, q, scal, part, blockIdx.y);
 }
 
-// x += [S_XALPHA2 pp2 +] S_XALPHA p for the active cases (one case per
-// blockIdx.y): the directions still owed to the iterate.
-template <typename T, bool TWO>
+// x += sum_j S_XALPHA+j pend[j] over the NP directions still owed to the
+// iterate, for the active cases (one case per blockIdx.y).
+template <typename T, int NP>
 __global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict__ x,
-                                                     const T* __restrict__ pp2,
-                                                     const T* __restrict__ p, const double* scal) {
+                                                     const Pending<T> pend, const double* scal) {
   const int c = blockIdx.y;
   if (!case_on(scal, c)) return;
-  const double xa = scal[S_XALPHA * 8 + c];
-  const double xb = TWO ? scal[S_XALPHA2 * 8 + c] : 0.0;
+  double xa[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) xa[j] = scal[(S_XALPHA + j) * 8 + c];
   const int64_t n = g.n;
   const int64_t base = (int64_t)c * 3 * n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -141,17 +150,17 @@ __global__ void __launch_bounds__(VB) flush_x_kernel(Grid g, double* __restrict_
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const int64_t o = base + (int64_t)k * n + i;
-      if (TWO)
-        x[o] += xb * (double)pp2[o] + xa * (double)p[o];
-      else
-        x[o] += xa * (double)p[o];
+      double dx = xa[NP - 1] * (double)pend.d[NP - 1][o];
+#pragma unroll
+      for (int j = NP - 2; j >= 0; --j) dx += xa[j] * (double)pend.d[j][o];
+      x[o] += dx;
     }
 }
 
 __global__ void __launch_bounds__(VB) update_batched_kernel(const PwBatchCell* __restrict__ cells) {
   // blockIdx.y = cell * NCASE + load case; x += alpha p every iteration
   const PwBatchCell& ce = cells[blockIdx.y / NCASE];
-  update_case<float, 2>(ce.g, ce.x, nullptr, nullptr, ce.p, ce.r, ce.q, ce.scal, ce.part,
+  update_case<float, 2>(ce.g, ce.x, Pending<float>{}, ce.p, ce.r, ce.q, ce.scal, ce.part,
                         blockIdx.y % NCASE);
 }
 
@@ -450,40 +459,53 @@ template void vec_convert<bf16, double>(double*, const bf16*, int64_t, hipStream
 template void vec_convert<double, f16>(f16*, const double*, int64_t, hipStream_t);
 
 template <typename T>
-void vec_update_r3(const Grid& g, double* x, const T* pp2, const T* pprev, const T* p, T* r,
+void vec_update_r4(const Grid& g, double* x, const T* const* pend, int npend, const T* p, T* r,
                    const T* q, const double* scal, Partials part, int* nblk_out, hipStream_t st) {
   const int nb = blocks_for(g.n);
-  if (pprev && pp2)
-    hipLaunchKernelGGL((update2_kernel<T, 3>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
-                       p, r, q, scal, part);
-  else if (pprev)
-    hipLaunchKernelGGL((update2_kernel<T, 1>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
-                       p, r, q, scal, part);
-  else
-    hipLaunchKernelGGL((update2_kernel<T, 0>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pp2, pprev,
-                       p, r, q, scal, part);
+  Pending<T> pd{};
+  for (int j = 0; j < npend; ++j) pd.d[j] = pend[j];
+  switch (npend) {
+    case 0:
+      hipLaunchKernelGGL((update2_kernel<T, 0>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pd, p, r,
+                         q, scal, part);
+      break;
+    case 1:
+      hipLaunchKernelGGL((update2_kernel<T, 1>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pd, p, r,
+                         q, scal, part);
+      break;
+    case 2:
+      hipLaunchKernelGGL((update2_kernel<T, 3>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pd, p, r,
+                         q, scal, part);
+      break;
+    default:
+      hipLaunchKernelGGL((update2_kernel<T, 4>), dim3(nb, NCASE), dim3(VB), 0, st, g, x, pd, p, r,
+                         q, scal, part);
+  }
   *nblk_out = nb;
 }
 template <typename T>
-void vec_flush_x(const Grid& g, double* x, const T* pp2, const T* p, const double* scal,
+void vec_flush_x(const Grid& g, double* x, const T* const* pend, int npend, const double* scal,
                  hipStream_t st) {
-  if (pp2)
-    hipLaunchKernelGGL((flush_x_kernel<T, true>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st, g,
-                       x, pp2, p, scal);
-  else
-    hipLaunchKernelGGL((flush_x_kernel<T, false>), dim3(blocks_for(g.n), NCASE), dim3(VB), 0, st,
-                       g, x, pp2, p, scal);
+  Pending<T> pd{};
+  for (int j = 0; j < npend; ++j) pd.d[j] = pend[j];
+  const dim3 grid(blocks_for(g.n), NCASE);
+  if (npend == 1)
+    hipLaunchKernelGGL((flush_x_kernel<T, 1>), grid, dim3(VB), 0, st, g, x, pd, scal);
+  else if (npend == 2)
+    hipLaunchKernelGGL((flush_x_kernel<T, 2>), grid, dim3(VB), 0, st, g, x, pd, scal);
+  else if (npend == 3)
+    hipLaunchKernelGGL((flush_x_kernel<T, 3>), grid, dim3(VB), 0, st, g, x, pd, scal);
 }
-template void vec_update_r3<float>(const Grid&, double*, const float*, const float*, const float*,
+template void vec_update_r4<float>(const Grid&, double*, const float* const*, int, const float*,
                                    float*, const float*, const double*, Partials, int*,
                                    hipStream_t);
-template void vec_update_r3<double>(const Grid&, double*, const double*, const double*,
+template void vec_update_r4<double>(const Grid&, double*, const double* const*, int,
                                     const double*, double*, const double*, const double*, Partials,
                                     int*, hipStream_t);
-template void vec_flush_x<float>(const Grid&, double*, const float*, const float*, const double*,
+template void vec_flush_x<float>(const Grid&, double*, const float* const*, int, const double*,
                                  hipStream_t);
-template void vec_flush_x<double>(const Grid&, double*, const double*, const double*,
-                                  const double*, hipStream_t);
+template void vec_flush_x<double>(const Grid&, double*, const double* const*, int, const double*,
+                                  hipStream_t);
 
 template <typename R, typename D, typename Z>
 void vec_jacobi0(const Grid& g, const R* r, const D* dinv, Z* z, const double* scal,
